@@ -1,0 +1,202 @@
+/*
+ * he.h -- C ABI of the rotation-free HE Conv/FC server path on MI355X (gfx950).
+ *
+ * The library evaluates the server side of the paper's Conv and FC procedures
+ * (Alg. 1 "Proposed HE convolution procedure", server evaluation; Alg. 2
+ * "Proposed FC evaluation procedure with HE", server evaluation) in the exact
+ * BFV-style reading: R_q = Z_q[X]/(X^N + 1) over L RNS limbs of 30-bit primes,
+ * plaintext modulus t, Delta = floor(Q / t).
+ *
+ *   conv:  c0^(n) = sum_j c0_j rho_j^(n) - Delta sh_j fhat_j^(n)        (Alg. 1)
+ *          out_g  = residue class o_n of c0^(n) for the channels n of group g,
+ *                   zero elsewhere, plus Delta sh'_g                       (Alg. 1)
+ *   fc:    out_b  = first n_o' coefficients of c0 rho_b - Delta sh w_b,
+ *                   plus Delta ((d_b + sh'_b) mod t)                       (Alg. 2)
+ *
+ * Packing follows Eq. (k_batch_new) / Eq. (i_batch) for conv, generalised to
+ * c_o > c_i, zero padding and inputs wider than one polynomial:
+ *   H_p = H + 2 pad, W_p = W + 2 pad, s = 2^floor(log2(N / (H_p W_p))),
+ *   g_i = min(c_i, s), g_o = largest power of two <= min(c_o, s),
+ *   K_in = ceil(c_i / g_i), K_out = ceil(c_o / g_o), o_n = (n mod g_o) s / g_o.
+ *   Input poly j, coefficient s (y W_p + x) + m' holds channel j g_i + m' at
+ *   padded pixel (y, x); output channel n at output pixel (oy, ox) is
+ *   coefficient s (stride oy W_p + stride ox) + o_n of output poly n / g_o.
+ * and Eq. (i(x) formula) / Eq. (w(x) formula) with Theorem 1 for FC, with
+ *   n_o' = n_o rounded up to a power of two (or 2^floor(log2(N / n_i)) rows per
+ *   block when n_i n_o' > N), n_i' = N / n_o', blocks = ceil(n_o / n_o'),
+ *   input coefficient l n_o' holds input l.
+ *
+ * Conventions for every call:
+ *  - Polynomials at the boundary are in coefficient form, u32, contiguous,
+ *    limb-major (the limb axis sits just before the N axis), residues in
+ *    [0, q_l).  Shares sh / sh' hold values in [0, t) and carry no limb axis.
+ *  - Pointers named d_* are device memory owned by the caller; they must stay
+ *    valid until the stream reaches the call.  Host pointers are read before
+ *    the call returns.  The library owns contexts and layers.
+ *  - Layer calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Error codes are returned before any launch when the arguments
+ *    are invalid; nothing is written in that case.
+ *  - Contexts and layers are bound to the device that was current at creation.
+ */
+#ifndef HE_H
+#define HE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HE_OK = 0,
+    HE_EINVAL = -1,        /* invalid argument or parameter set            */
+    HE_EUNSUPPORTED = -2,  /* valid but outside what this build handles    */
+    HE_ENOMEM = -3,        /* device or host allocation failed             */
+    HE_EDEVICE = -4        /* a HIP runtime call or kernel launch failed   */
+};
+
+enum { HE_LAYER_CONV = 0, HE_LAYER_FC = 1 };
+
+/* he_pack_filters flags: which inverse transform the conv layer will use. */
+enum {
+    HE_PACK_CLASS_INTT = 0,  /* default: inverse transform only the extracted
+                                residue classes (Sec. III-A: only the valid
+                                slots need to be computed)                    */
+    HE_PACK_FULL_INTT = 1    /* full-length inverse NTT of every c0^(n), then
+                                extraction (Alg. 1 as printed)                */
+};
+
+typedef struct he_ctx he_ctx;
+typedef struct he_layer he_layer;
+
+typedef struct {
+    int32_t kind;                                 /* HE_LAYER_CONV or HE_LAYER_FC */
+    uint32_t c_i, c_o, H, W, f, stride, pad;      /* conv                         */
+    uint32_t n_i, n_o;                            /* fc                           */
+} he_layer_desc;
+
+typedef struct {
+    int32_t kind;
+    uint32_t N, L;
+    uint32_t s, g_i, g_o, K_in, K_out, H_p, W_p, H_o, W_o;   /* conv            */
+    uint32_t n_o_p, n_i_p, blocks;                          /* fc              */
+    uint32_t flags;                                         /* pack flags      */
+    uint64_t resident_bytes;                                /* device operands */
+} he_layer_info;
+
+/*
+ * he_setup -- create a context for ring degree N (a power of two, 256..16384),
+ * L limbs (1..8) and plaintext modulus t (2 <= t < every q).
+ * primes: L distinct primes q < 2^30 with q = 1 (mod 2N), or NULL for the L
+ * largest such primes in descending order.  Builds the twiddle tables on the
+ * current device.  (Sec. II-A ring R_Q and RNS/CRT of Sec. I; parameters of
+ * Sec. IV-A are replaced by the exact-integer set.)
+ * Returns HE_EINVAL for a bad parameter set, HE_EDEVICE / HE_ENOMEM on
+ * device failures.  *out is set only on HE_OK.
+ */
+int he_setup(uint32_t N, uint32_t L, const uint32_t *primes, uint32_t t, he_ctx **out);
+
+/* Parameters of a context: primes[L] and Delta mod q_l (delta_l[L]); either may be NULL. */
+int he_ctx_params(const he_ctx *ctx, uint32_t *N, uint32_t *L, uint32_t *t,
+                  uint32_t *primes, uint32_t *delta_l);
+
+/*
+ * he_pack_filters -- server initialisation of one layer (Alg. 1 / Alg. 2,
+ * server initialisation and the precomputed transforms of Sec. IV-A-1):
+ * pack the filters (conv) or weight matrix (fc), then keep the NTT-domain
+ * products operands resident on the device.
+ *   weights  host int8: conv [c_o][c_i][f][f]; fc [n_o][n_i]
+ *   rho      host u32 masks, values < t: conv [K_in][c_o][N]; fc [blocks][N]
+ *   bias     host int32 [n_o] (fc only; NULL = zero; must be NULL for conv)
+ *   flags    HE_PACK_CLASS_INTT or HE_PACK_FULL_INTT (conv only)
+ * Synchronises the device before returning.  The layer is owned by the
+ * library until he_free_layer.
+ */
+int he_pack_filters(he_ctx *ctx, const he_layer_desc *desc, const int8_t *weights,
+                    const uint32_t *rho, const int32_t *bias, uint32_t flags,
+                    he_layer **out);
+
+/* Tiling of a packed layer (the quantities in the comment at the top). */
+int he_layer_info_get(const he_layer *layer, he_layer_info *out);
+
+/* Bytes of device workspace a layer call with batch B needs (see *_ws calls). */
+size_t he_layer_workspace_bytes(const he_layer *layer, uint32_t B);
+
+/*
+ * he_conv_layer -- server evaluation of one Conv layer for B images
+ * (Alg. 1, server evaluation, and the extraction loops that follow it).
+ *   d_c0       [B][K_in][L][N]  c0 shares, residues < q_l
+ *   d_sh       [B][K_in][N]     server input share, values < t; NULL on a
+ *                               network's first layer (no share to remove)
+ *   d_sh_next  [B][K_out][N]    fresh server share sh', values < t; NULL on
+ *                               the last layer
+ *   d_out      [B][K_out][L][N] c0^r, residues < q_l
+ * Uses a workspace owned by the context (allocated on first use for the
+ * largest B seen; concurrent calls on different streams each get their own).
+ */
+int he_conv_layer(he_ctx *ctx, const he_layer *layer, uint32_t B,
+                  const uint32_t *d_c0, const uint32_t *d_sh, const uint32_t *d_sh_next,
+                  uint32_t *d_out, void *stream);
+
+/* As he_conv_layer with a caller-owned device workspace of at least
+ * he_layer_workspace_bytes(layer, B) bytes (256-byte aligned).  Allocates nothing. */
+int he_conv_layer_ws(he_ctx *ctx, const he_layer *layer, uint32_t B,
+                     const uint32_t *d_c0, const uint32_t *d_sh, const uint32_t *d_sh_next,
+                     uint32_t *d_out, void *d_workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * he_fc_layer -- server evaluation of one FC layer for B inputs (Alg. 2,
+ * server evaluation; Theorem 1 places output b n_o' + k at coefficient k of
+ * block b).
+ *   d_c0       [B][L][N]               c0 of the packed input (Eq. i(x) formula)
+ *   d_sh       [B][N] values < t, or NULL
+ *   d_sh_next  [B][blocks][n_o'] values < t, or NULL (last layer)
+ *   d_out      [B][blocks][L][n_o']    first n_o' coefficients of c0^r per block
+ */
+int he_fc_layer(he_ctx *ctx, const he_layer *layer, uint32_t B,
+                const uint32_t *d_c0, const uint32_t *d_sh, const uint32_t *d_sh_next,
+                uint32_t *d_out, void *stream);
+
+int he_fc_layer_ws(he_ctx *ctx, const he_layer *layer, uint32_t B,
+                   const uint32_t *d_c0, const uint32_t *d_sh, const uint32_t *d_sh_next,
+                   uint32_t *d_out, void *d_workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Transform primitives on device polynomials, exposed for checking the ring
+ * arithmetic (Sec. IV-A-1: products through NTTs and coefficient-wise
+ * multiplications).  d_in / d_out: [rows][L][N] u32 residues < q_l; may alias.
+ * The NTT-domain order is private to the library: only ntt followed by intt,
+ * or he_poly_mul, have a defined meaning in coefficient form.
+ */
+int he_ntt_forward(he_ctx *ctx, uint32_t rows, const uint32_t *d_in, uint32_t *d_out, void *stream);
+int he_ntt_inverse(he_ctx *ctx, uint32_t rows, const uint32_t *d_in, uint32_t *d_out, void *stream);
+/* d_c[r] = d_a[r] * d_b[r] in Z_q[X]/(X^N + 1), per limb; [rows][L][N] each.
+ * d_c must not alias d_a or d_b.  Uses the context workspace. */
+int he_poly_mul(he_ctx *ctx, uint32_t rows, const uint32_t *d_a, const uint32_t *d_b,
+                uint32_t *d_c, void *stream);
+
+/*
+ * Kernel timing (measurement aid).  While enabled for a kernel kind, every
+ * launch of that kind made by the layer calls is bracketed by two HIP events
+ * recorded on the call's stream.  he_profile_read synchronises on the recorded
+ * events and returns the number of launches and their summed duration (ms)
+ * since the last reset.  Kinds: HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL (residue-
+ * class inverse + extraction), HE_K_INTT (full inverse + extraction).
+ */
+enum { HE_K_NTT_FWD = 1, HE_K_MAC = 2, HE_K_TAIL = 4, HE_K_INTT = 8 };
+int he_profile_enable(he_ctx *ctx, uint32_t kind_mask);
+int he_profile_read(he_ctx *ctx, uint32_t kind, uint64_t *launches, double *total_ms);
+int he_profile_reset(he_ctx *ctx);
+
+void he_free_layer(he_layer *layer);
+void he_free(he_ctx *ctx);
+const char *he_strerror(int code);
+/* Text of the last HIP error seen by the library (thread-local), or "". */
+const char *he_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HE_H */

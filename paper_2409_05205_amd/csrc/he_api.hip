@@ -1,0 +1,717 @@
+// Host side of the C ABI declared in include/he.h.
+//
+// Context: primes (rule: the L largest q < 2^30 with q = 1 mod 2N), a primitive
+// 2N-th root psi per prime, Shoup twiddle tables in HBM ([L][N] words each),
+// Delta = floor(Q / t) mod q_l computed without big integers as
+// Delta = -(Q mod t) t^-1 (mod q_l), since q_l | Q.
+// Layer: packed filters (Eq. k_batch_new generalised, or Eq. w(x) formula), then
+// the NTT-domain operands kept resident: Op[n][l][J][N], J < K_in the masks
+// rho_j^(n), J >= K_in the products -Delta fhat_j^(n), all times N^-1 and, in
+// the residue-class form, times x_k^-o_n.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/he.h"
+#include "he_kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int dev_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return HE_EDEVICE;
+}
+
+#define HE_HIP(call)                                              \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return dev_fail(e_, #call);         \
+    } while (0)
+
+typedef unsigned __int128 u128;
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    a %= m;
+    while (e) {
+        if (e & 1) r = mulmod(r, a, m);
+        a = mulmod(a, a, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+uint64_t invmod(uint64_t a, uint64_t p) { return powmod(a, p - 2, p); }   // p prime
+
+bool is_prime_u64(uint64_t n) {
+    if (n < 2) return false;
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t p : bases)
+        if (n % p == 0) return n == p;
+    uint64_t d = n - 1;
+    int r = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++r;
+    }
+    for (uint64_t a : bases) {
+        uint64_t x = powmod(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < r; ++i) {
+            x = mulmod(x, x, n);
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+uint32_t bit_reverse(uint32_t x, int bits) {
+    uint32_t r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+    return r;
+}
+
+uint32_t shoup(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
+
+uint32_t log2u(uint32_t x) {
+    uint32_t r = 0;
+    while ((1u << r) < x) ++r;
+    return r;
+}
+
+uint32_t pow2_floor(uint32_t x) {
+    uint32_t r = 1;
+    while ((r << 1) <= x) r <<= 1;
+    return r;
+}
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct ProfRec {
+    uint32_t kind;
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct he_ctx {
+    int device = 0;
+    uint32_t N = 0, logN = 0, L = 0, t = 0;
+    std::vector<uint32_t> primes, delta_l;
+    LimbConsts lc;
+    uint32_t *tw = nullptr, *twsh = nullptr, *twi = nullptr, *twish = nullptr, *xinv = nullptr;
+    std::mutex mu;
+    std::unordered_map<hipStream_t, Workspace> ws;
+    uint32_t prof_mask = 0;
+    std::vector<ProfRec> prof;
+};
+
+struct he_layer {
+    he_ctx *ctx = nullptr;
+    he_layer_info info;
+    uint32_t *op = nullptr;        // [c_o or blocks][L][2 K_in][N]
+    int32_t *bias = nullptr;       // fc: [blocks][n_o_p]
+    uint32_t n_rows = 0;           // c_o (conv) or blocks (fc)
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t layer_ws_bytes(const he_layer *ly, uint32_t B) {
+    const he_layer_info &in = ly->info;
+    const size_t N = in.N, L = in.L;
+    if (in.kind == HE_LAYER_CONV) {
+        const size_t xn = align256((size_t)B * 2 * in.K_in * L * N * 4);
+        const size_t per = (in.flags == HE_PACK_FULL_INTT) ? N : N / in.s;
+        return xn + align256((size_t)B * ly->n_rows * L * per * 4);
+    }
+    return align256((size_t)B * 2 * L * N * 4) + align256((size_t)B * in.blocks * L * N * 4);
+}
+
+int ctx_workspace(he_ctx *ctx, hipStream_t st, size_t bytes, void **out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Workspace &w = ctx->ws[st];
+    if (w.bytes < bytes) {
+        if (w.ptr) HE_HIP(hipFree(w.ptr));
+        w.ptr = nullptr;
+        w.bytes = 0;
+        hipError_t e = hipMalloc(&w.ptr, bytes);
+        if (e != hipSuccess) {
+            w.ptr = nullptr;
+            g_last_error = std::string("workspace hipMalloc: ") + hipGetErrorString(e);
+            return HE_ENOMEM;
+        }
+        w.bytes = bytes;
+    }
+    *out = w.ptr;
+    return HE_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Brackets one kernel launch with events on its stream when profiling is on for its kind.
+struct ProfScope {
+    he_ctx *ctx;
+    uint32_t kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(he_ctx *c, uint32_t k, hipStream_t s) : ctx(c), kind(k), st(s) {
+        if (ctx->prof_mask & kind) {
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+                a = b = nullptr;
+                return;
+            }
+            hipEventRecord(a, st);
+        }
+    }
+    hipError_t done(hipError_t e) {
+        if (a) {
+            hipEventRecord(b, st);
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->prof.push_back({kind, a, b});
+            a = b = nullptr;
+        }
+        return e;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *he_strerror(int code) {
+    switch (code) {
+        case HE_OK: return "ok";
+        case HE_EINVAL: return "invalid argument";
+        case HE_EUNSUPPORTED: return "unsupported";
+        case HE_ENOMEM: return "out of memory";
+        case HE_EDEVICE: return "device error";
+        default: return "unknown error";
+    }
+}
+
+const char *he_last_error(void) { return g_last_error.c_str(); }
+
+int he_setup(uint32_t N, uint32_t L, const uint32_t *primes, uint32_t t, he_ctx **out) {
+    if (!out) return HE_EINVAL;
+    if (N < 256 || N > 16384 || (N & (N - 1))) return HE_EINVAL;
+    if (L < 1 || L > HE_MAX_LIMBS) return HE_EINVAL;
+    if (t < 2) return HE_EINVAL;
+    std::vector<uint32_t> ps;
+    if (primes) {
+        for (uint32_t l = 0; l < L; ++l) {
+            const uint32_t q = primes[l];
+            if (q >= (1u << 30) || q % (2 * N) != 1 || !is_prime_u64(q) || t >= q) return HE_EINVAL;
+            for (uint32_t p : ps)
+                if (p == q) return HE_EINVAL;
+            ps.push_back(q);
+        }
+    } else {
+        uint64_t q = (((1ull << 30) - 1) / (2 * N)) * (2 * N) + 1;
+        if (q >= (1ull << 30)) q -= 2 * N;
+        while (ps.size() < L && q > 2 * N) {
+            if (is_prime_u64(q)) ps.push_back((uint32_t)q);
+            q -= 2 * N;
+        }
+        if (ps.size() < L) return HE_EINVAL;
+        for (uint32_t p : ps)
+            if (t >= p) return HE_EINVAL;
+    }
+    he_ctx *ctx = new (std::nothrow) he_ctx();
+    if (!ctx) return HE_ENOMEM;
+    hipGetDevice(&ctx->device);
+    ctx->N = N;
+    ctx->logN = log2u(N);
+    ctx->L = L;
+    ctx->t = t;
+    ctx->primes = ps;
+    std::memset(&ctx->lc, 0, sizeof(ctx->lc));
+    uint64_t Qmodt = 1;
+    for (uint32_t q : ps) Qmodt = Qmodt * (q % t) % t;
+    std::vector<uint32_t> h_tw((size_t)L * N), h_twsh((size_t)L * N), h_twi((size_t)L * N), h_twish((size_t)L * N),
+        h_xinv((size_t)L * N);
+    const int bits = (int)ctx->logN;
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t q = ps[l];
+        // primitive 2N-th root: g^((q-1)/2N) with psi^N = -1
+        uint64_t psi = 0;
+        for (uint64_t g = 2; g < q; ++g) {
+            const uint64_t c = powmod(g, (q - 1) / (2 * N), q);
+            if (powmod(c, N, q) == q - 1) {
+                psi = c;
+                break;
+            }
+        }
+        if (!psi) {
+            delete ctx;
+            return HE_EINVAL;
+        }
+        const uint64_t psi_inv = invmod(psi, q);
+        for (uint32_t i = 0; i < N; ++i) {
+            const uint32_t e = bit_reverse(i, bits);
+            const uint32_t w = (uint32_t)powmod(psi, e, q);
+            const uint32_t wi = (uint32_t)powmod(psi_inv, e, q);
+            h_tw[(size_t)l * N + i] = w;
+            h_twsh[(size_t)l * N + i] = shoup(w, q);
+            h_twi[(size_t)l * N + i] = wi;
+            h_twish[(size_t)l * N + i] = shoup(wi, q);
+            // x_k^-1 with x_k = psi^(2 brv(k) + 1), the k-th evaluation point
+            h_xinv[(size_t)l * N + i] = (uint32_t)powmod(psi_inv, 2ull * e + 1, q);
+        }
+        LimbConst &c = ctx->lc.l[l];
+        c.q = q;
+        c.q2 = 2 * q;
+        const uint64_t dl = (q - mulmod(Qmodt % q, invmod(t % q, q), q)) % q;   // floor(Q/t) mod q
+        c.delta = (uint32_t)dl;
+        c.delta_sh = shoup(c.delta, q);
+        c.r32 = (uint32_t)((1ull << 32) % q);
+        c.r32_sh = shoup(c.r32, q);
+        c.bar = (uint32_t)((1ull << 32) / q);
+        c.ninv = (uint32_t)invmod(N, q);
+        c.ninv_sh = shoup(c.ninv, q);
+        c.t_mod = t;
+        ctx->delta_l.push_back(c.delta);
+    }
+    const size_t bytes = (size_t)L * N * 4;
+    uint32_t **bufs[5] = {&ctx->tw, &ctx->twsh, &ctx->twi, &ctx->twish, &ctx->xinv};
+    std::vector<uint32_t> *hosts[5] = {&h_tw, &h_twsh, &h_twi, &h_twish, &h_xinv};
+    for (int i = 0; i < 5; ++i) {
+        hipError_t e = hipMalloc((void **)bufs[i], bytes);
+        if (e == hipSuccess) e = hipMemcpy(*bufs[i], hosts[i]->data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            he_free(ctx);
+            return dev_fail(e, "he_setup tables");
+        }
+    }
+    *out = ctx;
+    return HE_OK;
+}
+
+int he_ctx_params(const he_ctx *ctx, uint32_t *N, uint32_t *L, uint32_t *t, uint32_t *primes, uint32_t *delta_l) {
+    if (!ctx) return HE_EINVAL;
+    if (N) *N = ctx->N;
+    if (L) *L = ctx->L;
+    if (t) *t = ctx->t;
+    for (uint32_t l = 0; l < ctx->L; ++l) {
+        if (primes) primes[l] = ctx->primes[l];
+        if (delta_l) delta_l[l] = ctx->delta_l[l];
+    }
+    return HE_OK;
+}
+
+int he_profile_enable(he_ctx *ctx, uint32_t kind_mask) {
+    if (!ctx) return HE_EINVAL;
+    ctx->prof_mask = kind_mask;
+    return HE_OK;
+}
+
+int he_profile_read(he_ctx *ctx, uint32_t kind, uint64_t *launches, double *total_ms) {
+    if (!ctx) return HE_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    uint64_t n = 0;
+    double tot = 0.0;
+    for (const ProfRec &r : ctx->prof) {
+        if (r.kind != kind) continue;
+        HE_HIP(hipEventSynchronize(r.stop));
+        float ms = 0.f;
+        HE_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+        tot += ms;
+        ++n;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = tot;
+    return HE_OK;
+}
+
+int he_profile_reset(he_ctx *ctx) {
+    if (!ctx) return HE_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (const ProfRec &r : ctx->prof) {
+        hipEventSynchronize(r.stop);
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    ctx->prof.clear();
+    return HE_OK;
+}
+
+void he_free(he_ctx *ctx) {
+    if (!ctx) return;
+    he_profile_reset(ctx);
+    hipFree(ctx->tw);
+    hipFree(ctx->twsh);
+    hipFree(ctx->twi);
+    hipFree(ctx->twish);
+    hipFree(ctx->xinv);
+    for (auto &kv : ctx->ws)
+        if (kv.second.ptr) hipFree(kv.second.ptr);
+    delete ctx;
+}
+
+void he_free_layer(he_layer *ly) {
+    if (!ly) return;
+    hipFree(ly->op);
+    hipFree(ly->bias);
+    delete ly;
+}
+
+int he_layer_info_get(const he_layer *ly, he_layer_info *out) {
+    if (!ly || !out) return HE_EINVAL;
+    *out = ly->info;
+    return HE_OK;
+}
+
+size_t he_layer_workspace_bytes(const he_layer *ly, uint32_t B) { return ly ? layer_ws_bytes(ly, B) : 0; }
+
+int he_pack_filters(he_ctx *ctx, const he_layer_desc *desc, const int8_t *weights, const uint32_t *rho,
+                    const int32_t *bias, uint32_t flags, he_layer **out) {
+    if (!ctx || !desc || !weights || !rho || !out) return HE_EINVAL;
+    if (flags != HE_PACK_CLASS_INTT && flags != HE_PACK_FULL_INTT) return HE_EINVAL;
+    const uint32_t N = ctx->N, L = ctx->L;
+    he_layer_info info;
+    std::memset(&info, 0, sizeof(info));
+    info.kind = desc->kind;
+    info.N = N;
+    info.L = L;
+    uint32_t K_in = 0, n_rows = 0;
+    std::vector<int16_t> fh;   // [K_in][n_rows][N]
+    std::vector<int32_t> hbias;
+    std::vector<uint32_t> cls;
+    if (desc->kind == HE_LAYER_CONV) {
+        if (bias) return HE_EINVAL;
+        const uint32_t c_i = desc->c_i, c_o = desc->c_o, H = desc->H, W = desc->W, f = desc->f;
+        const uint32_t st = desc->stride, pad = desc->pad;
+        if (!c_i || !c_o || !H || !W || !f || !st) return HE_EINVAL;
+        const uint64_t Hp = (uint64_t)H + 2 * pad, Wp = (uint64_t)W + 2 * pad;
+        if (f > Hp || f > Wp || Hp * Wp > N) return HE_EINVAL;
+        const uint32_t s = pow2_floor((uint32_t)(N / (Hp * Wp)));
+        if (s > 256) return HE_EUNSUPPORTED;
+        info.s = s;
+        info.g_i = c_i < s ? c_i : s;
+        info.g_o = pow2_floor(c_o < s ? c_o : s);
+        info.K_in = (c_i + info.g_i - 1) / info.g_i;
+        info.K_out = (c_o + info.g_o - 1) / info.g_o;
+        info.H_p = (uint32_t)Hp;
+        info.W_p = (uint32_t)Wp;
+        info.H_o = (uint32_t)((Hp - f) / st + 1);
+        info.W_o = (uint32_t)((Wp - f) / st + 1);
+        info.flags = flags;
+        K_in = info.K_in;
+        n_rows = c_o;
+        fh.assign((size_t)K_in * c_o * N, 0);
+        cls.resize(c_o);
+        for (uint32_t n = 0; n < c_o; ++n) {
+            const int64_t o_n = (int64_t)(n % info.g_o) * (s / info.g_o);
+            cls[n] = (uint32_t)o_n;
+            for (uint32_t m = 0; m < c_i; ++m) {
+                const uint32_t j = m / info.g_i, mp = m % info.g_i;
+                for (uint32_t ky = 0; ky < f; ++ky)
+                    for (uint32_t kx = 0; kx < f; ++kx) {
+                        const int32_t w = weights[(((size_t)n * c_i + m) * f + ky) * f + kx];
+                        const int64_t e = o_n - (int64_t)s * (ky * Wp + kx) - mp;
+                        int16_t &dst = fh[((size_t)j * c_o + n) * N + (size_t)(e >= 0 ? e : N + e)];
+                        dst = (int16_t)(dst + (e >= 0 ? w : -w));
+                    }
+            }
+        }
+    } else if (desc->kind == HE_LAYER_FC) {
+        const uint32_t n_i = desc->n_i, n_o = desc->n_o;
+        if (!n_i || !n_o || n_i > N) return HE_EINVAL;
+        uint32_t nop = 1;
+        while (nop < n_o) nop <<= 1;
+        if ((uint64_t)n_i * nop > N) nop = pow2_floor(N / n_i);
+        info.n_o_p = nop;
+        info.n_i_p = N / nop;
+        info.blocks = (n_o + nop - 1) / nop;
+        info.K_in = 1;
+        info.flags = HE_PACK_FULL_INTT;
+        K_in = 1;
+        n_rows = info.blocks;
+        fh.assign((size_t)info.blocks * N, 0);
+        hbias.assign((size_t)info.blocks * nop, 0);
+        // Eq. (w(x) formula) per block: w_b = sum_k W_{k,0} X^k - sum_k sum_{l>=1} W_{k, n_i'-l} X^(l n_o' + k)
+        for (uint32_t b = 0; b < info.blocks; ++b)
+            for (uint32_t k = 0; k < nop; ++k) {
+                const uint32_t row = b * nop + k;
+                if (row >= n_o) continue;
+                for (uint32_t col = 0; col < n_i; ++col) {
+                    const int32_t w = weights[(size_t)row * n_i + col];
+                    if (col == 0)
+                        fh[(size_t)b * N + k] = (int16_t)w;
+                    else
+                        fh[(size_t)b * N + (size_t)(info.n_i_p - col) * nop + k] = (int16_t)(-w);
+                }
+                if (bias) hbias[(size_t)b * nop + k] = bias[row];
+            }
+    } else {
+        return HE_EINVAL;
+    }
+
+    he_layer *ly = new (std::nothrow) he_layer();
+    if (!ly) return HE_ENOMEM;
+    ly->ctx = ctx;
+    ly->n_rows = n_rows;
+    const uint32_t Jtot = 2 * K_in;
+    const size_t op_words = (size_t)n_rows * L * Jtot * N;
+    info.resident_bytes = op_words * 4 + hbias.size() * 4;
+    ly->info = info;
+
+    uint32_t *d_rho = nullptr, *d_cls = nullptr;
+    int16_t *d_fh = nullptr;
+    auto fail = [&](hipError_t e, const char *what) {
+        hipFree(d_rho);
+        hipFree(d_fh);
+        hipFree(d_cls);
+        he_free_layer(ly);
+        return dev_fail(e, what);
+    };
+    hipError_t e;
+    const size_t rho_words = (size_t)K_in * n_rows * N;
+    if ((e = hipMalloc((void **)&ly->op, op_words * 4)) != hipSuccess) {
+        he_free_layer(ly);
+        g_last_error = "layer operands: out of device memory";
+        return HE_ENOMEM;
+    }
+    if ((e = hipMalloc((void **)&d_rho, rho_words * 4)) != hipSuccess) return fail(e, "pack rho");
+    if ((e = hipMalloc((void **)&d_fh, fh.size() * 2)) != hipSuccess) return fail(e, "pack fhat");
+    if ((e = hipMemcpy(d_rho, rho, rho_words * 4, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "pack rho copy");
+    if ((e = hipMemcpy(d_fh, fh.data(), fh.size() * 2, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "pack fhat copy");
+    if (!hbias.empty()) {
+        if ((e = hipMalloc((void **)&ly->bias, hbias.size() * 4)) != hipSuccess) return fail(e, "pack bias");
+        if ((e = hipMemcpy(ly->bias, hbias.data(), hbias.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(e, "pack bias copy");
+    }
+    if (desc->kind == HE_LAYER_CONV && flags == HE_PACK_CLASS_INTT) {
+        if ((e = hipMalloc((void **)&d_cls, cls.size() * 4)) != hipSuccess) return fail(e, "pack cls");
+        if ((e = hipMemcpy(d_cls, cls.data(), cls.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(e, "pack cls copy");
+    }
+    hipStream_t st = nullptr;
+    if ((e = launch_expand_operands(d_rho, d_fh, ly->op, K_in, n_rows, L, N, ctx->lc, st)) != hipSuccess)
+        return fail(e, "expand");
+    RowMap m;
+    m.J = Jtot;
+    m.L = L;
+    m.src_b = m.dst_b = (uint64_t)L * Jtot * N;
+    m.src_j = m.dst_j = N;
+    m.src_l = m.dst_l = (uint64_t)Jtot * N;
+    if ((e = launch_ntt_fwd((int)ctx->logN, ly->op, ly->op, m, n_rows * Jtot * L, ctx->tw, ctx->twsh, ctx->lc, st)) !=
+        hipSuccess)
+        return fail(e, "operand ntt");
+    if ((e = launch_scale_operands(ly->op, ctx->xinv, d_cls, Jtot, n_rows, L, N, ctx->lc, st)) != hipSuccess)
+        return fail(e, "operand scale");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(e, "pack sync");
+    hipFree(d_rho);
+    hipFree(d_fh);
+    hipFree(d_cls);
+    *out = ly;
+    return HE_OK;
+}
+
+int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                     const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
+    if (!aligned16(d_c0) || !aligned16(d_out) || !aligned16(d_ws)) return HE_EINVAL;
+    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
+    const he_layer_info &in = ly->info;
+    const uint32_t N = in.N, L = in.L, K_in = in.K_in, Jtot = 2 * K_in;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *xn = (uint32_t *)d_ws;
+    uint32_t *mac = (uint32_t *)((char *)d_ws + align256((size_t)B * Jtot * L * N * 4));
+    RowMap m;
+    m.J = K_in;
+    m.L = L;
+    m.src_b = (uint64_t)K_in * L * N;
+    m.src_j = (uint64_t)L * N;
+    m.src_l = N;
+    m.dst_b = (uint64_t)Jtot * L * N;
+    m.dst_j = (uint64_t)L * N;
+    m.dst_l = N;
+    hipError_t e;
+    if ((e = ProfScope(ctx, HE_K_NTT_FWD, st).done(launch_ntt_fwd((int)ctx->logN, d_c0, xn, m, B * K_in * L, ctx->tw, ctx->twsh, ctx->lc, st))) != hipSuccess)
+        return dev_fail(e, "conv ntt c0");
+    if (d_sh) {
+        RowMap ms = m;
+        ms.src_b = (uint64_t)K_in * N;
+        ms.src_j = N;
+        ms.src_l = 0;
+        if ((e = ProfScope(ctx, HE_K_NTT_FWD, st).done(launch_ntt_fwd((int)ctx->logN, d_sh, xn + (size_t)K_in * L * N, ms,
+                                B * K_in * L, ctx->tw, ctx->twsh, ctx->lc, st))) != hipSuccess)
+            return dev_fail(e, "conv ntt sh");
+    }
+    const uint32_t Juse = d_sh ? Jtot : K_in;
+    if (in.flags == HE_PACK_CLASS_INTT) {
+        if ((e = ProfScope(ctx, HE_K_MAC, st).done(
+                 launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, ctx->lc, st))) != hipSuccess)
+            return dev_fail(e, "conv mac");
+        if ((e = ProfScope(ctx, HE_K_TAIL, st).done(launch_tail_class(mac, d_out, d_sh_next, B, ly->n_rows, in.g_o,
+                 in.K_out, L, N, in.s, ctx->twi, ctx->twish, ctx->lc, st))) != hipSuccess)
+            return dev_fail(e, "conv tail");
+    } else {
+        if ((e = ProfScope(ctx, HE_K_MAC, st).done(
+                 launch_mac_full(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, ctx->lc, st))) != hipSuccess)
+            return dev_fail(e, "conv mac");
+        EpiParams ep;
+        std::memset(&ep, 0, sizeof(ep));
+        ep.c_o = ly->n_rows;
+        ep.g_o = in.g_o;
+        ep.K_out = in.K_out;
+        ep.s_log = log2u(in.s);
+        ep.out = d_out;
+        ep.sh_next = d_sh_next;
+        RowMap mi;
+        std::memset(&mi, 0, sizeof(mi));
+        mi.J = 1;
+        mi.L = L;
+        if ((e = ProfScope(ctx, HE_K_INTT, st).done(launch_ntt_inv((int)ctx->logN, mac, d_out, mi,
+                 B * in.K_out * in.g_o * L, ctx->twi, ctx->twish, ctx->lc, EPI_CONV_CLASS, ep, st))) != hipSuccess)
+            return dev_fail(e, "conv intt");
+    }
+    return HE_OK;
+}
+
+int he_conv_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                  const uint32_t *d_sh_next, uint32_t *d_out, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    void *ws = nullptr;
+    const size_t need = layer_ws_bytes(ly, B);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
+    if (rc != HE_OK) return rc;
+    return he_conv_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, stream);
+}
+
+int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                   const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_FC) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
+    if (!aligned16(d_c0) || !aligned16(d_ws)) return HE_EINVAL;
+    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
+    const he_layer_info &in = ly->info;
+    const uint32_t N = in.N, L = in.L;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *xn = (uint32_t *)d_ws;
+    uint32_t *mac = (uint32_t *)((char *)d_ws + align256((size_t)B * 2 * L * N * 4));
+    RowMap m;
+    m.J = 1;
+    m.L = L;
+    m.src_b = (uint64_t)L * N;
+    m.src_j = 0;
+    m.src_l = N;
+    m.dst_b = (uint64_t)2 * L * N;
+    m.dst_j = 0;
+    m.dst_l = N;
+    hipError_t e;
+    if ((e = ProfScope(ctx, HE_K_NTT_FWD, st).done(
+             launch_ntt_fwd((int)ctx->logN, d_c0, xn, m, B * L, ctx->tw, ctx->twsh, ctx->lc, st))) != hipSuccess)
+        return dev_fail(e, "fc ntt c0");
+    if (d_sh) {
+        RowMap ms = m;
+        ms.src_b = N;
+        ms.src_l = 0;
+        if ((e = ProfScope(ctx, HE_K_NTT_FWD, st).done(launch_ntt_fwd((int)ctx->logN, d_sh, xn + (size_t)L * N, ms,
+                 B * L, ctx->tw, ctx->twsh, ctx->lc, st))) != hipSuccess)
+            return dev_fail(e, "fc ntt sh");
+    }
+    if ((e = ProfScope(ctx, HE_K_MAC, st).done(
+             launch_mac_full(xn, ly->op, mac, B, 2, d_sh ? 2 : 1, in.blocks, L, N, ctx->lc, st))) != hipSuccess)
+        return dev_fail(e, "fc mac");
+    EpiParams ep;
+    std::memset(&ep, 0, sizeof(ep));
+    ep.n_o_p = in.n_o_p;
+    ep.blocks = in.blocks;
+    ep.out = d_out;
+    ep.sh_next = d_sh_next;
+    ep.bias = ly->bias;
+    RowMap mi;
+    std::memset(&mi, 0, sizeof(mi));
+    mi.J = 1;
+    mi.L = L;
+    if ((e = ProfScope(ctx, HE_K_INTT, st).done(launch_ntt_inv((int)ctx->logN, mac, d_out, mi, B * in.blocks * L,
+             ctx->twi, ctx->twish, ctx->lc, EPI_FC_PREFIX, ep, st))) != hipSuccess)
+        return dev_fail(e, "fc intt");
+    return HE_OK;
+}
+
+int he_fc_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                const uint32_t *d_sh_next, uint32_t *d_out, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_FC) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    void *ws = nullptr;
+    const size_t need = layer_ws_bytes(ly, B);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
+    if (rc != HE_OK) return rc;
+    return he_fc_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, stream);
+}
+
+int he_ntt_forward(he_ctx *ctx, uint32_t rows, const uint32_t *d_in, uint32_t *d_out, void *stream) {
+    if (!ctx || (rows && (!d_in || !d_out))) return HE_EINVAL;
+    RowMap m;
+    m.J = 1;
+    m.L = ctx->L;
+    m.src_b = m.dst_b = (uint64_t)ctx->L * ctx->N;
+    m.src_j = m.dst_j = 0;
+    m.src_l = m.dst_l = ctx->N;
+    hipError_t e = launch_ntt_fwd((int)ctx->logN, d_in, d_out, m, rows * ctx->L, ctx->tw, ctx->twsh, ctx->lc,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? HE_OK : dev_fail(e, "ntt forward");
+}
+
+int he_ntt_inverse(he_ctx *ctx, uint32_t rows, const uint32_t *d_in, uint32_t *d_out, void *stream) {
+    if (!ctx || (rows && (!d_in || !d_out))) return HE_EINVAL;
+    RowMap m;
+    m.J = 1;
+    m.L = ctx->L;
+    m.src_b = m.dst_b = (uint64_t)ctx->L * ctx->N;
+    m.src_j = m.dst_j = 0;
+    m.src_l = m.dst_l = ctx->N;
+    EpiParams ep;
+    std::memset(&ep, 0, sizeof(ep));
+    ep.scale = 1;
+    hipError_t e = launch_ntt_inv((int)ctx->logN, d_in, d_out, m, rows * ctx->L, ctx->twi, ctx->twish, ctx->lc,
+                                  EPI_STORE, ep, (hipStream_t)stream);
+    return e == hipSuccess ? HE_OK : dev_fail(e, "ntt inverse");
+}
+
+int he_poly_mul(he_ctx *ctx, uint32_t rows, const uint32_t *d_a, const uint32_t *d_b, uint32_t *d_c, void *stream) {
+    if (!ctx) return HE_EINVAL;
+    if (rows == 0) return HE_OK;
+    if (!d_a || !d_b || !d_c || d_c == d_a || d_c == d_b) return HE_EINVAL;
+    const size_t words = (size_t)rows * ctx->L * ctx->N;
+    void *ws = nullptr;
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, align256(words * 4) * 2, &ws);
+    if (rc != HE_OK) return rc;
+    uint32_t *A = (uint32_t *)ws;
+    uint32_t *Bv = (uint32_t *)((char *)ws + align256(words * 4));
+    if ((rc = he_ntt_forward(ctx, rows, d_a, A, stream)) != HE_OK) return rc;
+    if ((rc = he_ntt_forward(ctx, rows, d_b, Bv, stream)) != HE_OK) return rc;
+    hipError_t e = launch_pointwise_mul(A, Bv, A, rows, ctx->L, ctx->N, ctx->lc, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "pointwise");
+    return he_ntt_inverse(ctx, rows, A, d_c, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Launch interfaces of the HIP kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "he_device.h"
+
+// Maps a flat row id r to (b, j, l) with l = r % L, j = (r / L) % J, b = r / (L J)
+// and gives element strides of the source and destination polynomials.
+struct RowMap {
+    uint32_t J, L;
+    uint64_t src_b, src_j, src_l;
+    uint64_t dst_b, dst_j, dst_l;
+};
+
+// Epilogues of the inverse transform.
+enum EpiKind {
+    EPI_STORE = 0,        // dst row = result (optionally times N^-1)
+    EPI_CONV_CLASS = 1,   // write residue-class range of channel n into its output poly
+    EPI_FC_PREFIX = 2     // write first n_o' coefficients plus Delta (d + sh') mod t
+};
+
+struct EpiParams {
+    // geometry
+    uint32_t c_o, g_o, K_out, s_log, n_o_p, blocks;
+    // conv: out [B][K_out][L][N]; sh_next [B][K_out][N] or null
+    // fc:   out [B][blocks][L][n_o_p]; sh_next [B][blocks][n_o_p] or null; bias [blocks][n_o_p]
+    uint32_t *out;
+    const uint32_t *sh_next;
+    const int32_t *bias;
+    uint32_t scale;   // EPI_STORE: 1 = multiply by N^-1
+};
+
+// Forward negacyclic NTT (natural order in, bit-reversed order out), rows of N words.
+hipError_t launch_ntt_fwd(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
+                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st);
+
+// Inverse (bit-reversed in, natural out, unscaled unless EPI_STORE with scale).
+// For EPI_CONV_CLASS rows are (b, g, n', l) with l fastest; src is [B][c_o][L][N].
+// For EPI_FC_PREFIX rows are (b, blk, l); src is [B][blocks][L][N].
+hipError_t launch_ntt_inv(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
+                          const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
+                          int epi, const EpiParams &ep, hipStream_t st);
+
+// Pointwise MAC, full length: out[b][n][l][k] = sum_{J<Juse} X[b][J][l][k] * Op[n][l][J][k].
+hipError_t launch_mac_full(const uint32_t *X, const uint32_t *Op, uint32_t *out, uint32_t B, uint32_t Jtot,
+                           uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, const LimbConsts &lc,
+                           hipStream_t st);
+
+// Pointwise MAC folded over residue blocks of s slots:
+// h[b][n][l][blk] = sum_{J<Juse} sum_{u<s} X[b][J][l][blk s + u] * Op[n][l][J][blk s + u].
+hipError_t launch_mac_class(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
+                            uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s,
+                            const LimbConsts &lc, hipStream_t st);
+
+// Inverse transform of size N/s of each channel's folded vector, scattered to its residue
+// class of the output poly, plus Delta sh'.  One workgroup per (b, g, l).
+hipError_t launch_tail_class(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B,
+                             uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s,
+                             const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
+                             hipStream_t st);
+
+// Pack-time helpers.
+// Op[n][l][j][k]         = rho[j][n][k]                         for j < K_in
+// Op[n][l][K_in + j][k]  = -Delta_l fhat[j][n][k] mod q_l         (fhat int16)
+hipError_t launch_expand_operands(const uint32_t *rho, const int16_t *fhat, uint32_t *Op, uint32_t K_in,
+                                  uint32_t c_o, uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st);
+// Op[n][l][J][k] *= N^-1 * xinv[l][k]^cls(n)   (cls = nullptr: factor N^-1 only)
+hipError_t launch_scale_operands(uint32_t *Op, const uint32_t *xinv, const uint32_t *cls, uint32_t Jtot,
+                                 uint32_t c_o, uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st);
+// c[r][l][k] = a[r][l][k] * b[r][l][k] mod q_l
+hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t rows, uint32_t L,
+                                uint32_t N, const LimbConsts &lc, hipStream_t st);

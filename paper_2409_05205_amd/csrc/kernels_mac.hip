@@ -1,0 +1,282 @@
+// Coefficient-wise multiply-accumulate, residue-class inverse tail, and
+// pack-time operand kernels for gfx950.
+//
+// MAC (the c0 rho - Delta sh fhat products of Alg. 1 / Alg. 2 carried out as
+// coefficient-wise products in the NTT domain, Sec. IV-A-1): each thread owns
+// four consecutive NTT slots (one 16-byte load per operand row), accumulates
+// 32x32->64-bit products over the input polynomials J, and folds the 64-bit
+// sums back below q every 15 terms so they never overflow.
+//
+// Residue-class form: the inverse transform's first log2(s) stages over each
+// block of s slots are linear in the block, so the row of that block transform
+// that yields residue class c_n is folded into the resident operands at pack
+// time (factor N^-1 x_k^-c_n with x_k the k-th evaluation point).  The MAC then
+// also sums over the s slots of a block (in-thread, then across s/4 lanes with
+// wave shuffles), leaving N/s values per channel for an (N/s)-point tail.
+
+#include "he_kernels.h"
+
+namespace {
+
+constexpr int MAC_THREADS = 256;
+
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t q) { return csub(a + b, q); }
+
+// Accumulate four slots of rows J in [0, Juse) for one image.
+__device__ __forceinline__ void mac4(const uint32_t *__restrict__ x, size_t xstride,
+                                     const uint32_t *__restrict__ op, size_t opstride, uint32_t Juse,
+                                     const LimbConst &c, uint32_t (&r)[4]) {
+    uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    uint32_t cnt = 0;
+    for (uint32_t J = 0; J < Juse; ++J) {
+        const uint4 xv = *reinterpret_cast<const uint4 *>(x + (size_t)J * xstride);
+        const uint4 ov = *reinterpret_cast<const uint4 *>(op + (size_t)J * opstride);
+        a0 += (uint64_t)xv.x * ov.x;
+        a1 += (uint64_t)xv.y * ov.y;
+        a2 += (uint64_t)xv.z * ov.z;
+        a3 += (uint64_t)xv.w * ov.w;
+        if (++cnt == 15) {   // 15 q^2 + q < 2^64
+            a0 = reduce64(a0, c);
+            a1 = reduce64(a1, c);
+            a2 = reduce64(a2, c);
+            a3 = reduce64(a3, c);
+            cnt = 0;
+        }
+    }
+    r[0] = reduce64(a0, c);
+    r[1] = reduce64(a1, c);
+    r[2] = reduce64(a2, c);
+    r[3] = reduce64(a3, c);
+}
+
+__global__ void __launch_bounds__(MAC_THREADS)
+k_mac_full(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ out, uint32_t B,
+           uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, LimbConsts lc) {
+    const uint32_t k4 = (blockIdx.x * MAC_THREADS + threadIdx.x) * 4u;
+    if (k4 >= N) return;
+    const uint32_t l = blockIdx.y % L;
+    const uint32_t n = blockIdx.y / L;
+    const LimbConst c = lc.l[l];
+    const uint32_t *op = Op + (size_t)(n * L + l) * Jtot * N + k4;
+    for (uint32_t b = 0; b < B; ++b) {
+        const uint32_t *x = X + ((size_t)b * Jtot * L + l) * N + k4;
+        uint32_t r[4];
+        mac4(x, (size_t)L * N, op, N, Juse, c, r);
+        *reinterpret_cast<uint4 *>(out + ((size_t)(b * c_o + n) * L + l) * N + k4) = make_uint4(r[0], r[1], r[2], r[3]);
+    }
+}
+
+__global__ void __launch_bounds__(MAC_THREADS)
+k_mac_class(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ h, uint32_t B,
+            uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s_log, LimbConsts lc) {
+    // every lane stays alive to the shuffles; out-of-range lanes contribute zero
+    const uint32_t k4 = (blockIdx.x * MAC_THREADS + threadIdx.x) * 4u;
+    const bool live = k4 < N;
+    const uint32_t l = blockIdx.y % L;
+    const uint32_t n = blockIdx.y / L;
+    const LimbConst c = lc.l[l];
+    const uint32_t s = 1u << s_log;
+    const uint32_t M = N >> s_log;
+    const uint32_t *op = Op + (size_t)(n * L + l) * Jtot * N + k4;
+    for (uint32_t b = 0; b < B; ++b) {
+        uint32_t r[4] = {0, 0, 0, 0};
+        if (live) {
+            const uint32_t *x = X + ((size_t)b * Jtot * L + l) * N + k4;
+            mac4(x, (size_t)L * N, op, N, Juse, c, r);
+        }
+        uint32_t *hb = h + ((size_t)(b * c_o + n) * L + l) * M;
+        if (s == 1) {
+            if (live) *reinterpret_cast<uint4 *>(hb + k4) = make_uint4(r[0], r[1], r[2], r[3]);
+        } else if (s == 2) {
+            if (live) {
+                hb[k4 >> 1] = addmod(r[0], r[1], c.q);
+                hb[(k4 >> 1) + 1] = addmod(r[2], r[3], c.q);
+            }
+        } else {
+            uint32_t v = r[0] + r[1] + r[2] + r[3];     // [0, 4q)
+            v = csub(csub(v, c.q2), c.q);
+            const uint32_t lanes = s >> 2;               // lanes per block, <= 64
+            for (uint32_t w = 1; w < lanes; w <<= 1) v = addmod(v, (uint32_t)__shfl_xor((int)v, (int)w), c.q);
+            if (live && ((threadIdx.x & (lanes - 1)) == 0)) hb[k4 >> s_log] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t mul_delta(uint32_t m, const LimbConst &c) {
+    return csub(shoup_lazy(m, c.delta, c.delta_sh, c.q), c.q);
+}
+
+constexpr int TAIL_THREADS = 256;
+
+__global__ void __launch_bounds__(TAIL_THREADS)
+k_tail_class(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const uint32_t *__restrict__ sh_next,
+             uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log,
+             const uint32_t *__restrict__ twi, const uint32_t *__restrict__ twish, LimbConsts lc) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t r = blockIdx.x;
+    const uint32_t l = r % L;
+    const uint32_t g = (r / L) % K_out;
+    const uint32_t b = r / (L * K_out);
+    const LimbConst c = lc.l[l];
+    const uint32_t N = 1u << logN;
+    const uint32_t logM = logN - s_log;
+    const uint32_t M = 1u << logM;
+    const uint32_t tot = g_o * M;
+    for (uint32_t i = tid; i < tot; i += TAIL_THREADS) {
+        const uint32_t np = i >> logM, m = i & (M - 1);
+        const uint32_t n = g * g_o + np;
+        lds[i] = (n < c_o) ? h[((size_t)(b * c_o + n) * L + l) * M + m] : 0u;
+    }
+    __syncthreads();
+    const uint32_t *W = twi + (size_t)l * N;
+    const uint32_t *Wsh = twish + (size_t)l * N;
+    const uint32_t nb = tot >> 1;
+    for (uint32_t k = 0; k < logM; ++k) {
+        const uint32_t t = 1u << k;
+        for (uint32_t bi = tid; bi < nb; bi += TAIL_THREADS) {
+            const uint32_t np = bi >> (logM - 1);
+            const uint32_t i = bi & ((M >> 1) - 1);
+            const uint32_t j = ((i >> k) << (k + 1)) | (i & (t - 1));
+            const uint32_t top = np * M + j;
+            const uint32_t ti = (M >> (k + 1)) + (j >> (k + 1));
+            uint32_t x = lds[top], y = lds[top + t];
+            gs_bfly(x, y, W[ti], Wsh[ti], c.q, c.q2);
+            lds[top] = x;
+            lds[top + t] = y;
+        }
+        __syncthreads();
+    }
+    const uint32_t s = 1u << s_log;
+    const uint32_t cls_w = s / g_o;
+    uint32_t *o = out + ((size_t)(b * K_out + g) * L + l) * N;
+    const uint32_t *sh = sh_next ? sh_next + (size_t)(b * K_out + g) * N : nullptr;
+    for (uint32_t idx = tid; idx < N; idx += TAIL_THREADS) {
+        const uint32_t cc = idx & (s - 1);
+        const uint32_t m = idx >> s_log;
+        uint32_t val = 0;
+        if ((cc & (cls_w - 1)) == 0) {
+            const uint32_t np = cc / cls_w;
+            if (g * g_o + np < c_o) val = csub(lds[np * M + m], c.q);
+        }
+        if (sh) val = addmod(val, mul_delta(sh[idx], c), c.q);
+        o[idx] = val;
+    }
+}
+
+// ------------------------------------------------------------------ pack-time kernels
+__device__ __forceinline__ uint32_t mulmod_slow(uint32_t a, uint32_t b, uint32_t q) {
+    return (uint32_t)(((uint64_t)a * b) % q);
+}
+
+__global__ void k_expand(const uint32_t *__restrict__ rho, const int16_t *__restrict__ fhat, uint32_t *__restrict__ Op,
+                         uint32_t K_in, uint32_t c_o, uint32_t L, uint32_t N, LimbConsts lc) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t row = blockIdx.y;          // (n, l, J)
+    const uint32_t Jtot = 2 * K_in;
+    const uint32_t J = row % Jtot;
+    const uint32_t l = (row / Jtot) % L;
+    const uint32_t n = row / (Jtot * L);
+    const LimbConst c = lc.l[l];
+    uint32_t v;
+    if (J < K_in) {
+        v = rho[((size_t)J * c_o + n) * N + k];
+    } else {
+        const int32_t f = fhat[((size_t)(J - K_in) * c_o + n) * N + k];
+        const uint32_t a = mulmod_slow((uint32_t)(f < 0 ? -f : f), c.delta, c.q);
+        // -Delta f mod q
+        v = (f > 0) ? (a == 0 ? 0u : c.q - a) : a;
+    }
+    Op[(size_t)row * N + k] = v;
+}
+
+__global__ void k_scale(uint32_t *__restrict__ Op, const uint32_t *__restrict__ xinv, const uint32_t *__restrict__ cls,
+                        uint32_t Jtot, uint32_t L, uint32_t N, LimbConsts lc) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t row = blockIdx.y;          // (n, l, J)
+    const uint32_t l = (row / Jtot) % L;
+    const uint32_t n = row / (Jtot * L);
+    const LimbConst c = lc.l[l];
+    uint32_t fac = c.ninv;
+    if (cls) {
+        uint32_t e = cls[n];
+        uint32_t base = xinv[(size_t)l * N + k];
+        uint32_t p = 1;
+        while (e) {
+            if (e & 1) p = mulmod_slow(p, base, c.q);
+            base = mulmod_slow(base, base, c.q);
+            e >>= 1;
+        }
+        fac = mulmod_slow(fac, p, c.q);
+    }
+    Op[(size_t)row * N + k] = mulmod_slow(Op[(size_t)row * N + k], fac, c.q);
+}
+
+__global__ void k_pointwise(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b, uint32_t *__restrict__ cc,
+                            uint32_t L, uint32_t N, LimbConsts lc) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t row = blockIdx.y;          // (r, l)
+    const uint32_t l = row % L;
+    const size_t i = (size_t)row * N + k;
+    cc[i] = reduce64((uint64_t)a[i] * b[i], lc.l[l]);
+}
+
+}  // namespace
+
+hipError_t launch_mac_full(const uint32_t *X, const uint32_t *Op, uint32_t *out, uint32_t B, uint32_t Jtot,
+                           uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, const LimbConsts &lc,
+                           hipStream_t st) {
+    if (B == 0) return hipSuccess;
+    dim3 grid((N / 4 + MAC_THREADS - 1) / MAC_THREADS, c_o * L);
+    hipLaunchKernelGGL(k_mac_full, grid, dim3(MAC_THREADS), 0, st, X, Op, out, B, Jtot, Juse, c_o, L, N, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_mac_class(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
+                            uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
+                            hipStream_t st) {
+    if (B == 0) return hipSuccess;
+    uint32_t s_log = 0;
+    while ((1u << s_log) < s) ++s_log;
+    if (s > 256) return hipErrorInvalidValue;   // s/4 lanes must fit one wave
+    dim3 grid((N / 4 + MAC_THREADS - 1) / MAC_THREADS, c_o * L);
+    hipLaunchKernelGGL(k_mac_class, grid, dim3(MAC_THREADS), 0, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_class(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
+                             uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
+                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st) {
+    if (B == 0) return hipSuccess;
+    uint32_t logN = 0, s_log = 0;
+    while ((1u << logN) < N) ++logN;
+    while ((1u << s_log) < s) ++s_log;
+    const size_t lds = (size_t)g_o * (N >> s_log) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_tail_class, dim3(B * K_out * L), dim3(TAIL_THREADS), lds, st, h, out, sh_next, c_o, g_o,
+                       K_out, L, logN, s_log, twi, twish, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_operands(const uint32_t *rho, const int16_t *fhat, uint32_t *Op, uint32_t K_in, uint32_t c_o,
+                                  uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st) {
+    dim3 grid((N + 255) / 256, c_o * L * 2 * K_in);
+    hipLaunchKernelGGL(k_expand, grid, dim3(256), 0, st, rho, fhat, Op, K_in, c_o, L, N, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_operands(uint32_t *Op, const uint32_t *xinv, const uint32_t *cls, uint32_t Jtot, uint32_t c_o,
+                                 uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st) {
+    dim3 grid((N + 255) / 256, c_o * L * Jtot);
+    hipLaunchKernelGGL(k_scale, grid, dim3(256), 0, st, Op, xinv, cls, Jtot, L, N, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t rows, uint32_t L,
+                                uint32_t N, const LimbConsts &lc, hipStream_t st) {
+    dim3 grid((N + 255) / 256, rows * L);
+    hipLaunchKernelGGL(k_pointwise, grid, dim3(256), 0, st, a, b, c, L, N, lc);
+    return hipGetLastError();
+}

@@ -1,0 +1,320 @@
+"""ctypes binding of libhe.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module checks shapes, dtypes
+and devices, passes raw pointers and the caller's HIP stream, and turns error
+codes into exceptions.  Device buffers are torch tensors of dtype int32 holding
+the u32 residue words (all residues are below 2^30).  There is no CPU
+fallback: if the library is missing, importing the entry points fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhe.so")
+
+HE_OK, HE_EINVAL, HE_EUNSUPPORTED, HE_ENOMEM, HE_EDEVICE = 0, -1, -2, -3, -4
+HE_LAYER_CONV, HE_LAYER_FC = 0, 1
+HE_PACK_CLASS_INTT, HE_PACK_FULL_INTT = 0, 1
+
+EXPORTED = [
+    "he_setup", "he_ctx_params", "he_pack_filters", "he_layer_info_get", "he_layer_workspace_bytes",
+    "he_conv_layer", "he_conv_layer_ws", "he_fc_layer", "he_fc_layer_ws", "he_ntt_forward",
+    "he_ntt_inverse", "he_poly_mul", "he_free_layer", "he_free", "he_strerror", "he_last_error",
+    "he_profile_enable", "he_profile_read", "he_profile_reset",
+]
+HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT = 1, 2, 4, 8
+
+
+class HEError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {code} ({detail})" if detail else f"{what}: {code}")
+
+
+class LayerDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("c_i", ctypes.c_uint32), ("c_o", ctypes.c_uint32),
+                ("H", ctypes.c_uint32), ("W", ctypes.c_uint32), ("f", ctypes.c_uint32),
+                ("stride", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("n_i", ctypes.c_uint32),
+                ("n_o", ctypes.c_uint32)]
+
+
+class LayerInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("N", ctypes.c_uint32), ("L", ctypes.c_uint32),
+                ("s", ctypes.c_uint32), ("g_i", ctypes.c_uint32), ("g_o", ctypes.c_uint32),
+                ("K_in", ctypes.c_uint32), ("K_out", ctypes.c_uint32), ("H_p", ctypes.c_uint32),
+                ("W_p", ctypes.c_uint32), ("H_o", ctypes.c_uint32), ("W_o", ctypes.c_uint32),
+                ("n_o_p", ctypes.c_uint32), ("n_i_p", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("resident_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P, U32, VP, SZ = ctypes.POINTER, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
+    lib.he_setup.argtypes = [U32, U32, P(U32), U32, P(VP)]
+    lib.he_ctx_params.argtypes = [VP, P(U32), P(U32), P(U32), P(U32), P(U32)]
+    lib.he_pack_filters.argtypes = [VP, P(LayerDesc), VP, VP, VP, U32, P(VP)]
+    lib.he_layer_info_get.argtypes = [VP, P(LayerInfo)]
+    lib.he_layer_workspace_bytes.argtypes = [VP, U32]
+    lib.he_layer_workspace_bytes.restype = SZ
+    for name in ("he_conv_layer", "he_fc_layer"):
+        getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
+    for name in ("he_conv_layer_ws", "he_fc_layer_ws"):
+        getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP, SZ, VP]
+    lib.he_ntt_forward.argtypes = [VP, U32, VP, VP, VP]
+    lib.he_ntt_inverse.argtypes = [VP, U32, VP, VP, VP]
+    lib.he_poly_mul.argtypes = [VP, U32, VP, VP, VP, VP]
+    lib.he_profile_enable.argtypes = [VP, U32]
+    lib.he_profile_read.argtypes = [VP, U32, P(ctypes.c_uint64), P(ctypes.c_double)]
+    lib.he_profile_reset.argtypes = [VP]
+    lib.he_free_layer.argtypes = [VP]
+    lib.he_free.argtypes = [VP]
+    lib.he_strerror.argtypes = [ctypes.c_int]
+    lib.he_strerror.restype = ctypes.c_char_p
+    lib.he_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("he_layer_workspace_bytes", "he_strerror", "he_last_error", "he_free", "he_free_layer"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != HE_OK:
+        lib = load_library()
+        raise HEError(rc, what, f"{lib.he_strerror(rc).decode()}; {lib.he_last_error().decode()}")
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _check_dev(t, shape, name: str, allow_none: bool = False):
+    import torch
+    if t is None:
+        if allow_none:
+            return
+        raise ValueError(f"{name} is required")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise ValueError(f"{name} must hold 32-bit words (int32/uint32), got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+@dataclass
+class ConvSpec:
+    c_i: int
+    c_o: int
+    H: int
+    W: int
+    f: int = 3
+    stride: int = 1
+    pad: int = 1
+
+
+@dataclass
+class FCSpec:
+    n_i: int
+    n_o: int
+
+
+class Layer:
+    """A packed layer: NTT-domain operands resident on the device."""
+
+    def __init__(self, ctx: "Context", handle: int, kind: int):
+        self.ctx = ctx
+        self.handle = ctypes.c_void_p(handle)
+        self.kind = kind
+        info = LayerInfo()
+        _check(load_library().he_layer_info_get(self.handle, ctypes.byref(info)), "he_layer_info_get")
+        self.info = info
+
+    def __getattr__(self, k):
+        info = self.__dict__.get("info")
+        if info is not None and k in dict(LayerInfo._fields_):
+            return getattr(info, k)
+        raise AttributeError(k)
+
+    def workspace_bytes(self, B: int) -> int:
+        return int(load_library().he_layer_workspace_bytes(self.handle, B))
+
+    def free(self):
+        if self.handle:
+            load_library().he_free_layer(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """he_setup: ring degree N, L limbs of 30-bit NTT primes, plaintext modulus t."""
+
+    def __init__(self, N: int, L: int, t: int = 786433, primes: Optional[Sequence[int]] = None):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        parr = None if primes is None else (ctypes.c_uint32 * L)(*[int(p) for p in primes])
+        _check(lib.he_setup(N, L, parr, t, ctypes.byref(h)), "he_setup")
+        self.handle = h
+        ps = (ctypes.c_uint32 * L)()
+        ds = (ctypes.c_uint32 * L)()
+        _check(lib.he_ctx_params(h, None, None, None, ps, ds), "he_ctx_params")
+        self.N, self.L, self.t = N, L, t
+        self.primes = [int(x) for x in ps]
+        self.delta_l = [int(x) for x in ds]
+
+    # ---------------------------------------------------------- packing
+    def pack_conv(self, spec, weights: np.ndarray, rho: np.ndarray, flags: int = HE_PACK_CLASS_INTT) -> Layer:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.int8))
+        if w.shape != (spec.c_o, spec.c_i, spec.f, spec.f):
+            raise ValueError(f"weights shape {w.shape}")
+        r = np.ascontiguousarray(np.asarray(rho, dtype=np.uint32))
+        d = LayerDesc(HE_LAYER_CONV, spec.c_i, spec.c_o, spec.H, spec.W, spec.f, spec.stride, spec.pad, 0, 0)
+        info = self.conv_tiling(spec)
+        if r.shape != (info["K_in"], spec.c_o, self.N):
+            raise ValueError(f"rho shape {r.shape}, expected {(info['K_in'], spec.c_o, self.N)}")
+        h = ctypes.c_void_p()
+        _check(load_library().he_pack_filters(self.handle, ctypes.byref(d), w.ctypes.data, r.ctypes.data, None,
+                                              flags, ctypes.byref(h)), "he_pack_filters")
+        return Layer(self, h.value, HE_LAYER_CONV)
+
+    def pack_fc(self, spec, weights: np.ndarray, rho: np.ndarray, bias: Optional[np.ndarray] = None) -> Layer:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.int8))
+        if w.shape != (spec.n_o, spec.n_i):
+            raise ValueError(f"weights shape {w.shape}")
+        r = np.ascontiguousarray(np.asarray(rho, dtype=np.uint32))
+        b = None if bias is None else np.ascontiguousarray(np.asarray(bias, dtype=np.int32))
+        d = LayerDesc(HE_LAYER_FC, 0, 0, 0, 0, 0, 0, 0, spec.n_i, spec.n_o)
+        h = ctypes.c_void_p()
+        _check(load_library().he_pack_filters(self.handle, ctypes.byref(d), w.ctypes.data, r.ctypes.data,
+                                              None if b is None else b.ctypes.data, 0, ctypes.byref(h)),
+               "he_pack_filters")
+        return Layer(self, h.value, HE_LAYER_FC)
+
+    def conv_tiling(self, spec) -> dict:
+        """The tiling rule of include/he.h (host arithmetic only, for sizing buffers)."""
+        Hp, Wp = spec.H + 2 * spec.pad, spec.W + 2 * spec.pad
+        s = 1 << ((self.N // (Hp * Wp)).bit_length() - 1)
+        g_i = min(spec.c_i, s)
+        g_o = 1 << (min(spec.c_o, s).bit_length() - 1)
+        return dict(s=s, g_i=g_i, g_o=g_o, K_in=-(-spec.c_i // g_i), K_out=-(-spec.c_o // g_o))
+
+    # ---------------------------------------------------------- layer calls
+    def conv_layer(self, layer: Layer, c0, sh=None, sh_next=None, out=None, stream=None, workspace=None):
+        import torch
+        B = c0.shape[0]
+        i = layer.info
+        _check_dev(c0, (B, i.K_in, self.L, self.N), "c0")
+        _check_dev(sh, (B, i.K_in, self.N), "sh", True)
+        _check_dev(sh_next, (B, i.K_out, self.N), "sh_next", True)
+        if out is None:
+            out = torch.empty((B, i.K_out, self.L, self.N), dtype=torch.int32, device=c0.device)
+        _check_dev(out, (B, i.K_out, self.L, self.N), "out")
+        lib = load_library()
+        if workspace is None:
+            rc = lib.he_conv_layer(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out),
+                                   _stream(stream))
+        else:
+            rc = lib.he_conv_layer_ws(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out),
+                                      _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream))
+        _check(rc, "he_conv_layer")
+        return out
+
+    def fc_layer(self, layer: Layer, c0, sh=None, sh_next=None, out=None, stream=None, workspace=None):
+        import torch
+        B = c0.shape[0]
+        i = layer.info
+        _check_dev(c0, (B, self.L, self.N), "c0")
+        _check_dev(sh, (B, self.N), "sh", True)
+        _check_dev(sh_next, (B, i.blocks, i.n_o_p), "sh_next", True)
+        if out is None:
+            out = torch.empty((B, i.blocks, self.L, i.n_o_p), dtype=torch.int32, device=c0.device)
+        _check_dev(out, (B, i.blocks, self.L, i.n_o_p), "out")
+        lib = load_library()
+        if workspace is None:
+            rc = lib.he_fc_layer(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out),
+                                 _stream(stream))
+        else:
+            rc = lib.he_fc_layer_ws(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out),
+                                    _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream))
+        _check(rc, "he_fc_layer")
+        return out
+
+    # ---------------------------------------------------------- primitives
+    def ntt_forward(self, x, out=None, stream=None):
+        import torch
+        rows = x.shape[0]
+        _check_dev(x, (rows, self.L, self.N), "x")
+        out = torch.empty_like(x) if out is None else out
+        _check(load_library().he_ntt_forward(self.handle, rows, _ptr(x), _ptr(out), _stream(stream)), "he_ntt_forward")
+        return out
+
+    def ntt_inverse(self, x, out=None, stream=None):
+        import torch
+        rows = x.shape[0]
+        _check_dev(x, (rows, self.L, self.N), "x")
+        out = torch.empty_like(x) if out is None else out
+        _check(load_library().he_ntt_inverse(self.handle, rows, _ptr(x), _ptr(out), _stream(stream)), "he_ntt_inverse")
+        return out
+
+    def poly_mul(self, a, b, out=None, stream=None):
+        import torch
+        rows = a.shape[0]
+        _check_dev(a, (rows, self.L, self.N), "a")
+        _check_dev(b, (rows, self.L, self.N), "b")
+        out = torch.empty_like(a) if out is None else out
+        _check(load_library().he_poly_mul(self.handle, rows, _ptr(a), _ptr(b), _ptr(out), _stream(stream)),
+               "he_poly_mul")
+        return out
+
+    # ---------------------------------------------------------- kernel timing
+    def profile_enable(self, kind_mask: int) -> None:
+        _check(load_library().he_profile_enable(self.handle, kind_mask), "he_profile_enable")
+
+    def profile_read(self, kind: int):
+        n = ctypes.c_uint64()
+        ms = ctypes.c_double()
+        _check(load_library().he_profile_read(self.handle, kind, ctypes.byref(n), ctypes.byref(ms)),
+               "he_profile_read")
+        return int(n.value), float(ms.value)
+
+    def profile_reset(self) -> None:
+        _check(load_library().he_profile_reset(self.handle), "he_profile_reset")
+
+    def free(self):
+        if getattr(self, "handle", None):
+            load_library().he_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
