@@ -63,6 +63,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    # torch brings its own HIP runtime (soname libamdhip64.so.7); loading it first makes
+    # libhe.so bind to that same runtime, so one process never holds two HIP runtimes.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, U32, VP, SZ = ctypes.POINTER, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
     lib.he_setup.argtypes = [U32, U32, P(U32), U32, P(VP)]
