@@ -1,0 +1,318 @@
+#!/usr/bin/env python
+"""Benchmark of the rotation-free HE Conv/FC server path on one MI355X.
+
+Workload (the `value` line): the full plain-20 x1 linear stack (19 convs + FC
+64->10), ring degree N = 8192 with 4 limbs of 30-bit primes, t = 786433, one
+image per layer call.  A step is one image through all 20 server layers (the
+whole hot path: forward NTTs, coefficient-wise MAC, residue-class inverse
+transform and extraction).  Inputs are synthetic and resident in HBM before
+timing: c0 shares uniform per limb (indistinguishable from real encryptions),
+shares uniform in [0, t), uint4-activation-shaped layers, weights in [-7, 7].
+
+Forms reported beside the value:
+  plain_host  one he_*_layer call per layer from Python, synchronising after each
+  plain       one image, the 20 layer calls issued back to back by the native runtime
+  graph       the same 20 calls captured once into a HIP graph, one replay per image
+  batched     64 images through the x1, x2 (N = 8192, 4 limbs) and x4 (N = 16384,
+              6 limbs) stacks, heads of 10 and 100 classes, graph replay per variant
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as wl  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ stack setup
+class Stack:
+    """Packed layers and resident per-image inputs of one plain-20 variant."""
+
+    def __init__(self, he, ctx, cfg, width, classes_list, B_list, N, L):
+        import torch
+        self.ctx = ctx
+        self.layers_shape = wl.plain20(width, classes_list[0])
+        self.layers = []
+        self.steps = []          # (layer, B, c0, sh, sh_next)
+        self.rows = []           # output channels (conv) or row blocks (fc) per step
+        dev = torch.device("cuda:0")
+        t = ctx.t
+        for k, shp in enumerate(self.layers_shape):
+            first, last = k == 0, k == len(self.layers_shape) - 1
+            if shp.kind == "conv":
+                spec = he.ConvSpec(shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
+                til = ctx.conv_tiling(spec)
+                W = wl.layer_weights(cfg, width, k, shp)
+                rho = wl.mask_polys(cfg, width, k, til["K_in"] * shp.c_o, N).reshape(til["K_in"], shp.c_o, N)
+                ly = ctx.pack_conv(spec, W, rho)
+                self.layers.append(ly)
+                B = sum(B_list)
+                c0 = torch.from_numpy(wl.ciphertext_polys(cfg, 0, width, k, B * til["K_in"], ctx.primes, N)
+                                      .reshape(B, til["K_in"], L, N).astype(np.int32)).to(dev)
+                sh = None if first else torch.from_numpy(
+                    wl.share_polys(cfg, 0, width, k, B * til["K_in"], N).reshape(B, til["K_in"], N)
+                    .astype(np.int32)).to(dev)
+                shn = None if last else torch.from_numpy(
+                    wl.share_polys(cfg, 0, width, k, B * til["K_out"], N, "shnext").reshape(B, til["K_out"], N)
+                    .astype(np.int32)).to(dev)
+                self.steps.append((ly, B, c0, sh, shn))
+                self.rows.append(shp.c_o)
+            else:
+                for h, (classes, B) in enumerate(zip(classes_list, B_list)):
+                    fshp = wl.FCShape(shp.n_i, classes)
+                    W = wl.layer_weights(cfg, width * 10 + h, k, fshp)
+                    bias = wl.layer_bias(cfg, width * 10 + h, k, fshp)
+                    nop = 1 << (classes - 1).bit_length()
+                    if shp.n_i * nop > N:
+                        nop = 1 << ((N // shp.n_i).bit_length() - 1)
+                    blocks = -(-classes // nop)
+                    rho = wl.mask_polys(cfg, width * 10 + h, k, blocks, N)
+                    ly = ctx.pack_fc(he.FCSpec(shp.n_i, classes), W, rho, bias)
+                    self.layers.append(ly)
+                    c0 = torch.from_numpy(wl.ciphertext_polys(cfg, 0, width * 10 + h, k, B, ctx.primes, N)
+                                          .astype(np.int32)).to(dev)
+                    sh = torch.from_numpy(wl.share_polys(cfg, 0, width * 10 + h, k, B, N).astype(np.int32)).to(dev)
+                    self.steps.append((ly, B, c0, sh, None))
+                    self.rows.append(blocks)
+        self.seq = he.Sequence(ctx)
+        for ly, B, c0, sh, shn in self.steps:
+            self.seq.add(ly, c0, sh, shn)
+
+    def image_layers(self):
+        """Image-layer evaluations per pass (conv layers count B images, FC heads their B)."""
+        return sum(B for _, B, _, _, _ in self.steps)
+
+    def mac_bytes(self):
+        """Algorithmic bytes of the MAC kernels in one pass: resident operands once,
+        NTT-domain inputs and MAC outputs once per image."""
+        tot = 0
+        L, N = self.ctx.L, self.ctx.N
+        for (ly, B, c0, sh, shn), c_o in zip(self.steps, self.rows):
+            i = ly.info
+            J = i.K_in * (2 if sh is not None else 1)
+            out_per = N // i.s if ly.kind == 0 else N
+            tot += J * c_o * L * N * 4 + B * J * L * N * 4 + B * c_o * L * out_per * 4
+        return tot
+
+    def modmuls(self):
+        """Coefficient-wise modular multiplications of the MAC in one pass."""
+        tot = 0
+        L, N = self.ctx.L, self.ctx.N
+        for (ly, B, c0, sh, shn), c_o in zip(self.steps, self.rows):
+            J = ly.info.K_in * (2 if sh is not None else 1)
+            tot += B * J * c_o * L * N
+        return tot
+
+
+def time_loop(fn, steps, warmup, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+# ------------------------------------------------------------------ CPU baseline
+def cpu_baseline(n_layers=3):
+    """The oracle's server evaluation of the first layers of the x1 stack on host cores."""
+    from oracle import bfv, packing
+    ctx = bfv.make_ctx(8192, 4, wl.T_PLAIN)
+    layers = wl.plain20(1, 10)
+    cfg = wl.CONFIG_PLAIN20_X1
+    t_tot = 0.0
+    for k in range(n_layers):
+        shp = layers[k]
+        g = packing.conv_geometry(8192, shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
+        F = wl.layer_weights(cfg, 1, k, shp)
+        rho = wl.mask_polys(cfg, 1, k, g.K_in * shp.c_o, 8192).reshape(g.K_in, shp.c_o, 8192)
+        c0 = wl.ciphertext_polys(cfg, 0, 1, k, g.K_in, ctx.primes, 8192).astype(np.uint64)
+        sh = None if k == 0 else wl.share_polys(cfg, 0, 1, k, g.K_in, 8192)
+        shn = wl.share_polys(cfg, 0, 1, k, g.K_out, 8192, "shnext")
+        fh = packing.pack_conv_filters(F, g)
+        t0 = time.perf_counter()
+        bfv.server_conv(ctx, g, c0, rho, fh, sh, shn)
+        t_tot += time.perf_counter() - t0
+    return {"value": n_layers / t_tot, "unit": "layers/s", "cores": 1, "kind": "oracle",
+            "sample": f"numpy oracle server evaluation of layers 0-{n_layers - 1} of the x1 stack "
+                      f"(one image, N=8192, 4 limbs), {t_tot:.1f} s single-threaded"}
+
+
+# ------------------------------------------------------------------ main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards across GPUs by "
+              f"independent requests, which this benchmark does not exercise", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_05205_amd import he
+    he.load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    sync = torch.cuda.synchronize
+
+    # ---------------- plain x1 stack, one image per call
+    log("setup: x1 stack N=8192 L=4")
+    ctx = he.Context(8192, 4, wl.T_PLAIN)
+    st = Stack(he, ctx, wl.CONFIG_PLAIN20_X1, 1, [10], [1], 8192, 4)
+    n_layers = len(st.steps)
+    sync()
+
+    # plain: native runtime, one image, 20 calls back to back
+    with torch.cuda.stream(stream):
+        T_plain = time_loop(lambda: st.seq.run(stream), args.steps, args.warmup, sync)
+    log(f"plain: {T_plain / args.steps * 1e3:.3f} ms/step")
+
+    # kernel timing of the same calls (HIP events on the launch stream)
+    ctx.profile_reset()
+    ctx.profile_enable(he.HE_K_MAC | he.HE_K_NTT_FWD | he.HE_K_TAIL | he.HE_K_INTT)
+    with torch.cuda.stream(stream):
+        T_prof = time_loop(lambda: st.seq.run(stream), args.steps, 0, sync)
+    kern = {}
+    for name, kind in [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL),
+                       ("intt", he.HE_K_INTT)]:
+        n, ms = ctx.profile_read(kind)
+        kern[name] = {"launches": n, "total_ms": ms, "avg_us": (ms * 1e3 / n) if n else None}
+    ctx.profile_enable(0)
+    ctx.profile_reset()
+    log("kernels:", json.dumps(kern))
+
+    # graph: capture once, replay per image
+    seq_g = he.Sequence(ctx)
+    for ly, B, c0, sh, shn in st.steps:
+        seq_g.add(ly, c0, sh, shn)
+    with torch.cuda.stream(stream):
+        seq_g.capture(stream)
+        T_graph = time_loop(lambda: seq_g.replay(stream), args.steps, args.warmup, sync)
+    log(f"graph: {T_graph / args.steps * 1e3:.3f} ms/step")
+
+    # plain_host: per-layer Python calls with a sync after each layer, per-layer latency
+    lat = []
+
+    def host_step():
+        for ly, B, c0, sh, shn in st.steps:
+            t0 = time.perf_counter()
+            if ly.kind == he.HE_LAYER_CONV:
+                ctx.conv_layer(ly, c0, sh, shn, stream=stream)
+            else:
+                ctx.fc_layer(ly, c0, sh, shn, stream=stream)
+            stream.synchronize()
+            lat.append(time.perf_counter() - t0)
+    host_steps = max(5, args.steps // 4)
+    T_host = time_loop(host_step, host_steps, 2, sync)
+    lat = lat[2 * n_layers:]
+    log(f"plain_host: {T_host / host_steps * 1e3:.3f} ms/step")
+
+    mac_bytes = st.mac_bytes()
+    mac_launches_per_step = n_layers
+    mac_avg_s = kern["mac"]["total_ms"] / 1e3 / kern["mac"]["launches"]
+    achieved = mac_bytes / mac_launches_per_step / mac_avg_s / 1e9
+    layers_per_s = n_layers * args.steps / T_plain
+    graph_lps = n_layers * args.steps / T_graph
+    result = {
+        "metric": "HE Conv+FC layers/sec and p50/p99 latency, batched/served vs plain, 1 MI355X",
+        "value": round(layers_per_s, 1),
+        "unit": "layers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(T_plain / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "plain-20 x1 linear stack (19 conv + FC 64->10), one image per layer call",
+                   "N": 8192, "limbs": 4, "t": wl.T_PLAIN, "layers": n_layers, "images_per_step": 1,
+                   "form": "plain: native runtime issues the 20 layer calls back to back on one stream"},
+        "limb_poly_macs_per_s": round(st.modmuls() / 8192 * args.steps / T_plain, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_mac_class / k_mac_full (coefficient-wise MAC)",
+                     "algorithmic_bytes_per_step": mac_bytes, "launches_per_step": mac_launches_per_step,
+                     "avg_launch_us": round(mac_avg_s * 1e6, 3)},
+        "kernels": kern,
+        "forms": {
+            "plain": {"layers_per_s": round(layers_per_s, 1), "ms_per_image": round(T_plain / args.steps * 1e3, 4)},
+            "graph": {"layers_per_s": round(graph_lps, 1), "ms_per_image": round(T_graph / args.steps * 1e3, 4)},
+            "plain_host": {"layers_per_s": round(n_layers * host_steps / T_host, 1),
+                           "ms_per_image": round(T_host / host_steps * 1e3, 4),
+                           "layer_latency_p50_ms": round(percentile(lat, 50) * 1e3, 4),
+                           "layer_latency_p99_ms": round(percentile(lat, 99) * 1e3, 4)},
+        },
+    }
+    del seq_g
+
+    # ---------------- batched: 64 images x widths 1, 2, 4
+    if not args.no_batched:
+        bres = {}
+        tot_layers = 0
+        tot_time = 0.0
+        for width, N, L in [(1, 8192, 4), (2, 8192, 4), (4, 16384, 6)]:
+            log(f"setup: batched x{width} N={N} L={L}")
+            bctx = ctx if N == 8192 else he.Context(N, L, wl.T_PLAIN)
+            bst = Stack(he, bctx, wl.CONFIG_BATCHED, width, [10, 100], [32, 32], N, L)
+            sync()
+            bseq = he.Sequence(bctx)
+            for ly, B, c0, sh, shn in bst.steps:
+                bseq.add(ly, c0, sh, shn)
+            with torch.cuda.stream(stream):
+                bseq.capture(stream)
+                T = time_loop(lambda: bseq.replay(stream), args.batched_steps, 1, sync)
+            il = bst.image_layers()
+            bres[f"x{width}"] = {"layers_per_s": round(il * args.batched_steps / T, 1),
+                                 "ms_per_batch": round(T / args.batched_steps * 1e3, 3),
+                                 "image_layers_per_batch": il,
+                                 "limb_poly_macs_per_s": round(bst.modmuls() / N * args.batched_steps / T, 1)}
+            log(f"batched x{width}: {json.dumps(bres[f'x{width}'])}")
+            tot_layers += il * args.batched_steps
+            tot_time += T
+            del bseq, bst
+            torch.cuda.empty_cache()
+        bres["all_widths_layers_per_s"] = round(tot_layers / tot_time, 1)
+        result["forms"]["batched"] = bres
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -189,6 +189,25 @@ int he_profile_enable(he_ctx *ctx, uint32_t kind_mask);
 int he_profile_read(he_ctx *ctx, uint32_t kind, uint64_t *launches, double *total_ms);
 int he_profile_reset(he_ctx *ctx);
 
+/*
+ * Layer sequences (runtime): an ordered list of layer calls with their device
+ * buffers, run as one host call or captured once into a HIP graph and replayed.
+ * Steps run in order on one stream and share one sequence-owned workspace, so a
+ * sequence is for one stream at a time.  Buffers must stay valid while the
+ * sequence exists.  Capture needs a non-null stream and turns kernel timing off
+ * for the context; after capture no step can be added.
+ */
+typedef struct he_seq he_seq;
+int he_seq_create(he_ctx *ctx, he_seq **out);
+/* Append a conv or FC call (kind taken from the layer); arguments as he_conv_layer / he_fc_layer. */
+int he_seq_add(he_seq *seq, const he_layer *layer, uint32_t B, const uint32_t *d_c0,
+               const uint32_t *d_sh, const uint32_t *d_sh_next, uint32_t *d_out);
+int he_seq_run(he_seq *seq, void *stream);
+int he_seq_capture(he_seq *seq, void *stream);
+int he_seq_replay(he_seq *seq, void *stream);
+uint32_t he_seq_length(const he_seq *seq);
+void he_seq_free(he_seq *seq);
+
 void he_free_layer(he_layer *layer);
 void he_free(he_ctx *ctx);
 const char *he_strerror(int code);

@@ -27,6 +27,8 @@ EXPORTED = [
     "he_conv_layer", "he_conv_layer_ws", "he_fc_layer", "he_fc_layer_ws", "he_ntt_forward",
     "he_ntt_inverse", "he_poly_mul", "he_free_layer", "he_free", "he_strerror", "he_last_error",
     "he_profile_enable", "he_profile_read", "he_profile_reset",
+    "he_seq_create", "he_seq_add", "he_seq_run", "he_seq_capture", "he_seq_replay", "he_seq_length",
+    "he_seq_free",
 ]
 HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT = 1, 2, 4, 8
 
@@ -84,13 +86,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_profile_enable.argtypes = [VP, U32]
     lib.he_profile_read.argtypes = [VP, U32, P(ctypes.c_uint64), P(ctypes.c_double)]
     lib.he_profile_reset.argtypes = [VP]
+    lib.he_seq_create.argtypes = [VP, P(VP)]
+    lib.he_seq_add.argtypes = [VP, VP, U32, VP, VP, VP, VP]
+    lib.he_seq_run.argtypes = [VP, VP]
+    lib.he_seq_capture.argtypes = [VP, VP]
+    lib.he_seq_replay.argtypes = [VP, VP]
+    lib.he_seq_length.argtypes = [VP]
+    lib.he_seq_length.restype = U32
+    lib.he_seq_free.argtypes = [VP]
     lib.he_free_layer.argtypes = [VP]
     lib.he_free.argtypes = [VP]
     lib.he_strerror.argtypes = [ctypes.c_int]
     lib.he_strerror.restype = ctypes.c_char_p
     lib.he_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("he_layer_workspace_bytes", "he_strerror", "he_last_error", "he_free", "he_free_layer"):
+        if name not in ("he_layer_workspace_bytes", "he_strerror", "he_last_error", "he_free", "he_free_layer",
+                        "he_seq_length", "he_seq_free"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -314,6 +325,65 @@ class Context:
     def free(self):
         if getattr(self, "handle", None):
             load_library().he_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Sequence:
+    """A recorded list of layer calls (he_seq_*): eager run, or hipGraph capture and replay.
+
+    Keeps references to the layers and buffers it was given so they outlive it.
+    """
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(load_library().he_seq_create(ctx.handle, ctypes.byref(h)), "he_seq_create")
+        self.handle = h
+        self._keep = []
+
+    def add(self, layer: Layer, c0, sh=None, sh_next=None, out=None):
+        import torch
+        B = c0.shape[0]
+        i = layer.info
+        if layer.kind == HE_LAYER_CONV:
+            _check_dev(c0, (B, i.K_in, self.ctx.L, self.ctx.N), "c0")
+            _check_dev(sh, (B, i.K_in, self.ctx.N), "sh", True)
+            _check_dev(sh_next, (B, i.K_out, self.ctx.N), "sh_next", True)
+            shape = (B, i.K_out, self.ctx.L, self.ctx.N)
+        else:
+            _check_dev(c0, (B, self.ctx.L, self.ctx.N), "c0")
+            _check_dev(sh, (B, self.ctx.N), "sh", True)
+            _check_dev(sh_next, (B, i.blocks, i.n_o_p), "sh_next", True)
+            shape = (B, i.blocks, self.ctx.L, i.n_o_p)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.int32, device=c0.device)
+        _check_dev(out, shape, "out")
+        _check(load_library().he_seq_add(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next),
+                                         _ptr(out)), "he_seq_add")
+        self._keep.append((layer, c0, sh, sh_next, out))
+        return out
+
+    def run(self, stream=None):
+        _check(load_library().he_seq_run(self.handle, _stream(stream)), "he_seq_run")
+
+    def capture(self, stream):
+        _check(load_library().he_seq_capture(self.handle, _stream(stream)), "he_seq_capture")
+
+    def replay(self, stream=None):
+        _check(load_library().he_seq_replay(self.handle, _stream(stream)), "he_seq_replay")
+
+    def __len__(self):
+        return int(load_library().he_seq_length(self.handle))
+
+    def free(self):
+        if getattr(self, "handle", None):
+            load_library().he_seq_free(self.handle)
             self.handle = None
 
     def __del__(self):
