@@ -169,27 +169,23 @@ int ctx_workspace(he_ctx *ctx, hipStream_t st, size_t bytes, void **out) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-// Brackets one kernel launch with events on its stream when profiling is on for its kind.
+// Times one kernel launch with dispatch-recorded events when profiling is on for its kind.
 struct ProfScope {
     he_ctx *ctx;
     uint32_t kind;
-    hipStream_t st;
-    hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(he_ctx *c, uint32_t k, hipStream_t s) : ctx(c), kind(k), st(s) {
+    LaunchEv le;
+    ProfScope(he_ctx *c, uint32_t k) : ctx(c), kind(k) {
         if (ctx->prof_mask & kind) {
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-                a = b = nullptr;
-                return;
-            }
-            hipEventRecord(a, st);
+            if (hipEventCreate(&le.start) != hipSuccess || hipEventCreate(&le.stop) != hipSuccess)
+                le.start = le.stop = nullptr;
         }
     }
+    const LaunchEv *ev() const { return le.start ? &le : nullptr; }
     hipError_t done(hipError_t e) {
-        if (a) {
-            hipEventRecord(b, st);
+        if (le.start) {
             std::lock_guard<std::mutex> lk(ctx->mu);
-            ctx->prof.push_back({kind, a, b});
-            a = b = nullptr;
+            ctx->prof.push_back({kind, le.start, le.stop});
+            le.start = le.stop = nullptr;
         }
         return e;
     }
@@ -551,28 +547,35 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
     m.dst_j = (uint64_t)L * N;
     m.dst_l = N;
     hipError_t e;
-    if ((e = ProfScope(ctx, HE_K_NTT_FWD, st).done(launch_ntt_fwd((int)ctx->logN, d_c0, xn, m, B * K_in * L, ctx->tw, ctx->twsh, ctx->lc, st))) != hipSuccess)
+    ProfScope ps1(ctx, HE_K_NTT_FWD);
+        if ((e = ps1.done(launch_ntt_fwd((int)ctx->logN, d_c0, xn, m, B * K_in * L, ctx->tw, ctx->twsh, ctx->lc, st, ps1.ev()))) != hipSuccess)
         return dev_fail(e, "conv ntt c0");
     if (d_sh) {
         RowMap ms = m;
         ms.src_b = (uint64_t)K_in * N;
         ms.src_j = N;
         ms.src_l = 0;
-        if ((e = ProfScope(ctx, HE_K_NTT_FWD, st).done(launch_ntt_fwd((int)ctx->logN, d_sh, xn + (size_t)K_in * L * N, ms,
-                                B * K_in * L, ctx->tw, ctx->twsh, ctx->lc, st))) != hipSuccess)
+        ProfScope ps2(ctx, HE_K_NTT_FWD);
+        if ((e = ps2.done(launch_ntt_fwd((int)ctx->logN, d_sh, xn + (size_t)K_in * L * N, ms,
+                                B * K_in * L, ctx->tw, ctx->twsh, ctx->lc, st, ps2.ev()))) != hipSuccess)
             return dev_fail(e, "conv ntt sh");
     }
     const uint32_t Juse = d_sh ? Jtot : K_in;
     if (in.flags == HE_PACK_CLASS_INTT) {
-        if ((e = ProfScope(ctx, HE_K_MAC, st).done(
-                 launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, ctx->lc, st))) != hipSuccess)
+        ProfScope ps3(ctx, HE_K_MAC);
+        if ((e = ps3.done(launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, ctx->lc, st, ps3.ev()))) != hipSuccess)
             return dev_fail(e, "conv mac");
-        if ((e = ProfScope(ctx, HE_K_TAIL, st).done(launch_tail_class(mac, d_out, d_sh_next, B, ly->n_rows, in.g_o,
-                 in.K_out, L, N, in.s, ctx->twi, ctx->twish, ctx->lc, st))) != hipSuccess)
+        ProfScope ps4(ctx, HE_K_TAIL);
+        const bool rows_form = (ctx->logN - log2u(in.s)) >= 4;
+        e = rows_form ? launch_tail_rows(mac, d_out, d_sh_next, B, ly->n_rows, in.g_o, in.K_out, L, N, in.s, ctx->twi,
+                                         ctx->twish, ctx->lc, st, ps4.ev())
+                      : launch_tail_class(mac, d_out, d_sh_next, B, ly->n_rows, in.g_o, in.K_out, L, N, in.s,
+                                          ctx->twi, ctx->twish, ctx->lc, st, ps4.ev());
+        if ((e = ps4.done(e)) != hipSuccess)
             return dev_fail(e, "conv tail");
     } else {
-        if ((e = ProfScope(ctx, HE_K_MAC, st).done(
-                 launch_mac_full(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, ctx->lc, st))) != hipSuccess)
+        ProfScope ps5(ctx, HE_K_MAC);
+        if ((e = ps5.done(launch_mac_full(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, ctx->lc, st, ps5.ev()))) != hipSuccess)
             return dev_fail(e, "conv mac");
         EpiParams ep;
         std::memset(&ep, 0, sizeof(ep));
@@ -586,8 +589,9 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
         std::memset(&mi, 0, sizeof(mi));
         mi.J = 1;
         mi.L = L;
-        if ((e = ProfScope(ctx, HE_K_INTT, st).done(launch_ntt_inv((int)ctx->logN, mac, d_out, mi,
-                 B * in.K_out * in.g_o * L, ctx->twi, ctx->twish, ctx->lc, EPI_CONV_CLASS, ep, st))) != hipSuccess)
+        ProfScope ps6(ctx, HE_K_INTT);
+        if ((e = ps6.done(launch_ntt_inv((int)ctx->logN, mac, d_out, mi,
+                 B * in.K_out * in.g_o * L, ctx->twi, ctx->twish, ctx->lc, EPI_CONV_CLASS, ep, st, ps6.ev()))) != hipSuccess)
             return dev_fail(e, "conv intt");
     }
     return HE_OK;
@@ -626,19 +630,20 @@ int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *
     m.dst_j = 0;
     m.dst_l = N;
     hipError_t e;
-    if ((e = ProfScope(ctx, HE_K_NTT_FWD, st).done(
-             launch_ntt_fwd((int)ctx->logN, d_c0, xn, m, B * L, ctx->tw, ctx->twsh, ctx->lc, st))) != hipSuccess)
+    ProfScope ps7(ctx, HE_K_NTT_FWD);
+        if ((e = ps7.done(launch_ntt_fwd((int)ctx->logN, d_c0, xn, m, B * L, ctx->tw, ctx->twsh, ctx->lc, st, ps7.ev()))) != hipSuccess)
         return dev_fail(e, "fc ntt c0");
     if (d_sh) {
         RowMap ms = m;
         ms.src_b = N;
         ms.src_l = 0;
-        if ((e = ProfScope(ctx, HE_K_NTT_FWD, st).done(launch_ntt_fwd((int)ctx->logN, d_sh, xn + (size_t)L * N, ms,
-                 B * L, ctx->tw, ctx->twsh, ctx->lc, st))) != hipSuccess)
+        ProfScope ps8(ctx, HE_K_NTT_FWD);
+        if ((e = ps8.done(launch_ntt_fwd((int)ctx->logN, d_sh, xn + (size_t)L * N, ms,
+                 B * L, ctx->tw, ctx->twsh, ctx->lc, st, ps8.ev()))) != hipSuccess)
             return dev_fail(e, "fc ntt sh");
     }
-    if ((e = ProfScope(ctx, HE_K_MAC, st).done(
-             launch_mac_full(xn, ly->op, mac, B, 2, d_sh ? 2 : 1, in.blocks, L, N, ctx->lc, st))) != hipSuccess)
+    ProfScope ps9(ctx, HE_K_MAC);
+        if ((e = ps9.done(launch_mac_full(xn, ly->op, mac, B, 2, d_sh ? 2 : 1, in.blocks, L, N, ctx->lc, st, ps9.ev()))) != hipSuccess)
         return dev_fail(e, "fc mac");
     EpiParams ep;
     std::memset(&ep, 0, sizeof(ep));
@@ -651,8 +656,9 @@ int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *
     std::memset(&mi, 0, sizeof(mi));
     mi.J = 1;
     mi.L = L;
-    if ((e = ProfScope(ctx, HE_K_INTT, st).done(launch_ntt_inv((int)ctx->logN, mac, d_out, mi, B * in.blocks * L,
-             ctx->twi, ctx->twish, ctx->lc, EPI_FC_PREFIX, ep, st))) != hipSuccess)
+    ProfScope ps10(ctx, HE_K_INTT);
+        if ((e = ps10.done(launch_ntt_inv((int)ctx->logN, mac, d_out, mi, B * in.blocks * L,
+             ctx->twi, ctx->twish, ctx->lc, EPI_FC_PREFIX, ep, st, ps10.ev()))) != hipSuccess)
         return dev_fail(e, "fc intt");
     return HE_OK;
 }

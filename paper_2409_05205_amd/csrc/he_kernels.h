@@ -1,10 +1,25 @@
 // Launch interfaces of the HIP kernels (host side).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "he_device.h"
+
+// Optional timing events for one launch: recorded by the dispatch itself
+// (hipExtLaunchKernelGGL), so they add no packets between kernels.
+struct LaunchEv {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+#define HE_LAUNCH(ev, kernel, grid, block, lds, st, ...)                                                  \
+    do {                                                                                                  \
+        if ((ev) && (ev)->start)                                                                          \
+            hipExtLaunchKernelGGL(kernel, grid, block, lds, st, (ev)->start, (ev)->stop, 0, __VA_ARGS__); \
+        else                                                                                              \
+            hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);                                \
+    } while (0)
 
 // Maps a flat row id r to (b, j, l) with l = r % L, j = (r / L) % J, b = r / (L J)
 // and gives element strides of the source and destination polynomials.
@@ -34,32 +49,39 @@ struct EpiParams {
 
 // Forward negacyclic NTT (natural order in, bit-reversed order out), rows of N words.
 hipError_t launch_ntt_fwd(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
-                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st);
+                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Inverse (bit-reversed in, natural out, unscaled unless EPI_STORE with scale).
 // For EPI_CONV_CLASS rows are (b, g, n', l) with l fastest; src is [B][c_o][L][N].
 // For EPI_FC_PREFIX rows are (b, blk, l); src is [B][blocks][L][N].
 hipError_t launch_ntt_inv(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
                           const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
-                          int epi, const EpiParams &ep, hipStream_t st);
+                          int epi, const EpiParams &ep, hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Pointwise MAC, full length: out[b][n][l][k] = sum_{J<Juse} X[b][J][l][k] * Op[n][l][J][k].
 hipError_t launch_mac_full(const uint32_t *X, const uint32_t *Op, uint32_t *out, uint32_t B, uint32_t Jtot,
                            uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, const LimbConsts &lc,
-                           hipStream_t st);
+                           hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Pointwise MAC folded over residue blocks of s slots:
 // h[b][n][l][blk] = sum_{J<Juse} sum_{u<s} X[b][J][l][blk s + u] * Op[n][l][J][blk s + u].
 hipError_t launch_mac_class(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
                             uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s,
-                            const LimbConsts &lc, hipStream_t st);
+                            const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Inverse transform of size N/s of each channel's folded vector, scattered to its residue
 // class of the output poly, plus Delta sh'.  One workgroup per (b, g, l).
 hipError_t launch_tail_class(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B,
                              uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s,
                              const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
-                             hipStream_t st);
+                             hipStream_t st, const LaunchEv *ev = nullptr);
+
+// Residue-class tail on registers: one (N/s)-point inverse per channel vector, several
+// channel vectors per workgroup, coalesced scatter into the output poly (N/s >= 16).
+hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
+                            uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
+                            const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
+                            const LaunchEv *ev = nullptr);
 
 // Pack-time helpers.
 // Op[n][l][j][k]         = rho[j][n][k]                         for j < K_in

@@ -228,35 +228,35 @@ __global__ void k_pointwise(const uint32_t *__restrict__ a, const uint32_t *__re
 
 hipError_t launch_mac_full(const uint32_t *X, const uint32_t *Op, uint32_t *out, uint32_t B, uint32_t Jtot,
                            uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, const LimbConsts &lc,
-                           hipStream_t st) {
+                           hipStream_t st, const LaunchEv *ev) {
     if (B == 0) return hipSuccess;
     dim3 grid((N / 4 + MAC_THREADS - 1) / MAC_THREADS, c_o * L);
-    hipLaunchKernelGGL(k_mac_full, grid, dim3(MAC_THREADS), 0, st, X, Op, out, B, Jtot, Juse, c_o, L, N, lc);
+    HE_LAUNCH(ev, k_mac_full, grid, dim3(MAC_THREADS), 0, st, X, Op, out, B, Jtot, Juse, c_o, L, N, lc);
     return hipGetLastError();
 }
 
 hipError_t launch_mac_class(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
                             uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
-                            hipStream_t st) {
+                            hipStream_t st, const LaunchEv *ev) {
     if (B == 0) return hipSuccess;
     uint32_t s_log = 0;
     while ((1u << s_log) < s) ++s_log;
     if (s > 256) return hipErrorInvalidValue;   // s/4 lanes must fit one wave
     dim3 grid((N / 4 + MAC_THREADS - 1) / MAC_THREADS, c_o * L);
-    hipLaunchKernelGGL(k_mac_class, grid, dim3(MAC_THREADS), 0, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, lc);
+    HE_LAUNCH(ev, k_mac_class, grid, dim3(MAC_THREADS), 0, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, lc);
     return hipGetLastError();
 }
 
 hipError_t launch_tail_class(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
                              uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
-                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st) {
+                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
     if (B == 0) return hipSuccess;
     uint32_t logN = 0, s_log = 0;
     while ((1u << logN) < N) ++logN;
     while ((1u << s_log) < s) ++s_log;
     const size_t lds = (size_t)g_o * (N >> s_log) * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_tail_class, dim3(B * K_out * L), dim3(TAIL_THREADS), lds, st, h, out, sh_next, c_o, g_o,
-                       K_out, L, logN, s_log, twi, twish, lc);
+    HE_LAUNCH(ev, k_tail_class, dim3(B * K_out * L), dim3(TAIL_THREADS), lds, st, h, out, sh_next, c_o, g_o,
+              K_out, L, logN, s_log, twi, twish, lc);
     return hipGetLastError();
 }
 

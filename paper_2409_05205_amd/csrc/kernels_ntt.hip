@@ -292,58 +292,164 @@ struct NttCfg {
 
 template <int LOGN>
 hipError_t fwd_dispatch(const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
-                        const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st) {
+                        const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st,
+                        const LaunchEv *ev) {
     using C = NttCfg<LOGN>;
-    hipLaunchKernelGGL((k_ntt_fwd<LOGN, C::LOGR>), dim3(rows), dim3(C::T), 0, st, src, dst, map, tw, twsh, lc);
+    HE_LAUNCH(ev, (k_ntt_fwd<LOGN, C::LOGR>), dim3(rows), dim3(C::T), 0, st, src, dst, map, tw, twsh, lc);
     return hipGetLastError();
 }
 
 template <int LOGN>
 hipError_t inv_dispatch(const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
                         const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc, int epi,
-                        const EpiParams &ep, hipStream_t st) {
+                        const EpiParams &ep, hipStream_t st, const LaunchEv *ev) {
     using C = NttCfg<LOGN>;
     if (epi == EPI_STORE)
-        hipLaunchKernelGGL((k_ntt_inv<LOGN, C::LOGR, EPI_STORE>), dim3(rows), dim3(C::T), 0, st, src, dst, map, twi,
-                           twish, lc, ep);
+        HE_LAUNCH(ev, (k_ntt_inv<LOGN, C::LOGR, EPI_STORE>), dim3(rows), dim3(C::T), 0, st, src, dst, map, twi,
+                  twish, lc, ep);
     else if (epi == EPI_CONV_CLASS)
-        hipLaunchKernelGGL((k_ntt_inv<LOGN, C::LOGR, EPI_CONV_CLASS>), dim3(rows), dim3(C::T), 0, st, src, dst, map,
-                           twi, twish, lc, ep);
+        HE_LAUNCH(ev, (k_ntt_inv<LOGN, C::LOGR, EPI_CONV_CLASS>), dim3(rows), dim3(C::T), 0, st, src, dst, map,
+                  twi, twish, lc, ep);
     else
-        hipLaunchKernelGGL((k_ntt_inv<LOGN, C::LOGR, EPI_FC_PREFIX>), dim3(rows), dim3(C::T), 0, st, src, dst, map,
-                           twi, twish, lc, ep);
+        HE_LAUNCH(ev, (k_ntt_inv<LOGN, C::LOGR, EPI_FC_PREFIX>), dim3(rows), dim3(C::T), 0, st, src, dst, map,
+                  twi, twish, lc, ep);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ residue-class tail
+// Rows are channel vectors h[b][n][l][0..M) with M = N/s.  A workgroup of TPW
+// threads holds RW = TPW / T rows (T = M / R threads per row) of consecutive
+// channels n' of one output group (b, g, l); it inverts each row in registers
+// (unscaled Gentleman-Sande, twiddles = the first M entries of the N-point
+// inverse table), then writes the span of residue classes its channels own:
+// out_g[s m + c] for c in [c_lo, c_lo + RW s / g_o), every m < M.
+template <int LOGM, int LOGR>
+__global__ void __launch_bounds__(512)
+k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const uint32_t *__restrict__ sh_next,
+            uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, uint32_t RW,
+            const uint32_t *__restrict__ twi, const uint32_t *__restrict__ twish, LimbConsts lc) {
+    constexpr int M = 1 << LOGM;
+    constexpr int T = 1 << (LOGM - LOGR);
+    constexpr int MP = M + (M >> 5);
+    extern __shared__ uint32_t lds[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t row = tid / T;               // row within the workgroup
+    const uint32_t t = tid % T;
+    const uint32_t chunks = g_o / RW;
+    uint32_t w = blockIdx.x;
+    const uint32_t chunk = w % chunks;
+    w /= chunks;
+    const uint32_t l = w % L;
+    w /= L;
+    const uint32_t g = w % K_out;
+    const uint32_t b = w / K_out;
+    const LimbConst c = lc.l[l];
+    const uint32_t N = 1u << logN;
+    const uint32_t np0 = chunk * RW;             // first channel slot of this workgroup within the group
+    uint32_t *my = lds + row * MP;
+    const bool active = row < RW;
+    const uint32_t n = g * g_o + np0 + row;
+    const bool exists = active && n < c_o;
+    if (active) {
+        const uint32_t *src = h + ((size_t)(b * c_o + (exists ? n : 0)) * L + l) * M;
+#pragma unroll
+        for (int i = 0; i < (1 << LOGR); ++i) {
+            const uint32_t idx = t + i * T;
+            my[lpad(idx)] = exists ? src[idx] : 0u;
+        }
+    }
+    __syncthreads();
+    uint32_t v[1 << LOGR];
+    inv_pass<LOGM, LOGR, 0>(v, my, t, twi + (size_t)l * N, twish + (size_t)l * N, c.q, c.q2);
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < (1 << LOGR); ++i) my[lpad(inv_final_idx<LOGM, LOGR>(t, i))] = csub(v[i], c.q);
+    }
+    __syncthreads();
+    const uint32_t s = 1u << s_log;
+    const uint32_t cls_w = s / g_o;
+    const uint32_t span = RW * cls_w;
+    const uint32_t c_lo = np0 * cls_w;
+    uint32_t *o = out + ((size_t)(b * K_out + g) * L + l) * N;
+    const uint32_t *sh = sh_next ? sh_next + (size_t)(b * K_out + g) * N : nullptr;
+    const uint32_t total = span * M;
+    for (uint32_t e = tid; e < total; e += blockDim.x) {
+        const uint32_t m = e / span;
+        const uint32_t off = e - m * span;
+        const uint32_t r = off / cls_w;
+        uint32_t val = 0;
+        if (off - r * cls_w == 0 && g * g_o + np0 + r < c_o) val = lds[r * MP + lpad(m)];
+        const uint32_t k = (m << s_log) + c_lo + off;
+        if (sh) val = csub(val + mul_delta_msg(sh[k], c), c.q);
+        o[k] = val;
+    }
+}
+
+template <int LOGM>
+hipError_t tail_dispatch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
+                         uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log,
+                         const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
+                         const LaunchEv *ev) {
+    constexpr int LOGR = (LOGM <= 12) ? 4 : 5;
+    constexpr int T = 1 << (LOGM - LOGR);
+    constexpr int TPW = T < 256 ? 256 : T;
+    uint32_t RW = TPW / T;
+    if (RW > g_o) RW = g_o;
+    const uint32_t grid = B * K_out * L * (g_o / RW);
+    const size_t lds = (size_t)(TPW / T) * ((1u << LOGM) + (1u << LOGM >> 5)) * sizeof(uint32_t);
+    HE_LAUNCH(ev, (k_tail_rows<LOGM, LOGR>), dim3(grid), dim3(TPW), lds, st, h, out, sh_next, c_o, g_o, K_out, L,
+              logN, s_log, RW, twi, twish, lc);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_ntt_fwd(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
-                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st) {
+                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st,
+                          const LaunchEv *ev) {
     if (rows == 0) return hipSuccess;
     switch (logn) {
-        case 8: return fwd_dispatch<8>(src, dst, map, rows, tw, twsh, lc, st);
-        case 9: return fwd_dispatch<9>(src, dst, map, rows, tw, twsh, lc, st);
-        case 10: return fwd_dispatch<10>(src, dst, map, rows, tw, twsh, lc, st);
-        case 11: return fwd_dispatch<11>(src, dst, map, rows, tw, twsh, lc, st);
-        case 12: return fwd_dispatch<12>(src, dst, map, rows, tw, twsh, lc, st);
-        case 13: return fwd_dispatch<13>(src, dst, map, rows, tw, twsh, lc, st);
-        case 14: return fwd_dispatch<14>(src, dst, map, rows, tw, twsh, lc, st);
+        case 8: return fwd_dispatch<8>(src, dst, map, rows, tw, twsh, lc, st, ev);
+        case 9: return fwd_dispatch<9>(src, dst, map, rows, tw, twsh, lc, st, ev);
+        case 10: return fwd_dispatch<10>(src, dst, map, rows, tw, twsh, lc, st, ev);
+        case 11: return fwd_dispatch<11>(src, dst, map, rows, tw, twsh, lc, st, ev);
+        case 12: return fwd_dispatch<12>(src, dst, map, rows, tw, twsh, lc, st, ev);
+        case 13: return fwd_dispatch<13>(src, dst, map, rows, tw, twsh, lc, st, ev);
+        case 14: return fwd_dispatch<14>(src, dst, map, rows, tw, twsh, lc, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_ntt_inv(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
                           const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc, int epi,
-                          const EpiParams &ep, hipStream_t st) {
+                          const EpiParams &ep, hipStream_t st, const LaunchEv *ev) {
     if (rows == 0) return hipSuccess;
     switch (logn) {
-        case 8: return inv_dispatch<8>(src, dst, map, rows, twi, twish, lc, epi, ep, st);
-        case 9: return inv_dispatch<9>(src, dst, map, rows, twi, twish, lc, epi, ep, st);
-        case 10: return inv_dispatch<10>(src, dst, map, rows, twi, twish, lc, epi, ep, st);
-        case 11: return inv_dispatch<11>(src, dst, map, rows, twi, twish, lc, epi, ep, st);
-        case 12: return inv_dispatch<12>(src, dst, map, rows, twi, twish, lc, epi, ep, st);
-        case 13: return inv_dispatch<13>(src, dst, map, rows, twi, twish, lc, epi, ep, st);
-        case 14: return inv_dispatch<14>(src, dst, map, rows, twi, twish, lc, epi, ep, st);
+        case 8: return inv_dispatch<8>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
+        case 9: return inv_dispatch<9>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
+        case 10: return inv_dispatch<10>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
+        case 11: return inv_dispatch<11>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
+        case 12: return inv_dispatch<12>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
+        case 13: return inv_dispatch<13>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
+        case 14: return inv_dispatch<14>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
+                            uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
+                            const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
+    if (B == 0) return hipSuccess;
+    uint32_t logN = 0, s_log = 0;
+    while ((1u << logN) < N) ++logN;
+    while ((1u << s_log) < s) ++s_log;
+    switch (logN - s_log) {
+#define HE_TAIL_CASE(LM) \
+    case LM: return tail_dispatch<LM>(h, out, sh_next, B, c_o, g_o, K_out, L, logN, s_log, twi, twish, lc, st, ev);
+        HE_TAIL_CASE(4) HE_TAIL_CASE(5) HE_TAIL_CASE(6) HE_TAIL_CASE(7) HE_TAIL_CASE(8) HE_TAIL_CASE(9)
+        HE_TAIL_CASE(10) HE_TAIL_CASE(11) HE_TAIL_CASE(12) HE_TAIL_CASE(13) HE_TAIL_CASE(14)
+#undef HE_TAIL_CASE
         default: return hipErrorInvalidValue;
     }
 }

@@ -45,6 +45,8 @@ SMALL_CONV = [
     (1024, 3, 16, 24, 6, 1),   # ragged last output group (g_o = 16), K_in = 1
     (1024, 2, 20, 4, 4, 1),    # K_in = 2 with a ragged input group, s = 16
     (1024, 2, 2, 2, 30, 1),    # s = 1: one class, full-length tail
+    (256, 2, 2, 32, 1, 1),     # 3x3 padded input: s = 16, tail of 16 points, one thread per row
+    (256, 2, 8, 16, (2, 2, 0), 1),  # 2x2 input, 2x2 filter, no padding: s = 64, 4-point tail
 ]
 
 
@@ -54,7 +56,10 @@ SMALL_CONV = [
 def test_conv_layer_matches_oracle(he, N, L, c_i, c_o, H, stride, flags, first, last):
     ctx = he.Context(N, L, T)
     octx = bfv.make_ctx(N, L, T)
-    g, F, rho, c0, sh, shn = _conv_case(octx, c_i, c_o, H, stride, N + c_i * 7 + c_o, first, last)
+    f, pad = 3, 1
+    if isinstance(H, tuple):
+        H, f, pad = H
+    g, F, rho, c0, sh, shn = _conv_case(octx, c_i, c_o, H, stride, N + c_i * 7 + c_o, first, last, f, pad)
     want = bfv.server_conv(octx, g, c0, rho, packing.pack_conv_filters(F, g), sh, shn)
     got = gpu_conv(ctx, g, F, rho, c0, sh, shn, flags)
     assert got.shape == want.shape
