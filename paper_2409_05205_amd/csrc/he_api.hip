@@ -563,7 +563,10 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
     const uint32_t Juse = d_sh ? Jtot : K_in;
     if (in.flags == HE_PACK_CLASS_INTT) {
         ProfScope ps3(ctx, HE_K_MAC);
-        if ((e = ps3.done(launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, ctx->lc, st, ps3.ev()))) != hipSuccess)
+        e = (B >= 4 && in.s <= 128)
+                ? launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, true, ctx->lc, st, ps3.ev())
+                : launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, ctx->lc, st, ps3.ev());
+        if ((e = ps3.done(e)) != hipSuccess)
             return dev_fail(e, "conv mac");
         ProfScope ps4(ctx, HE_K_TAIL);
         const bool rows_form = (ctx->logN - log2u(in.s)) >= 4;
@@ -575,7 +578,10 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
             return dev_fail(e, "conv tail");
     } else {
         ProfScope ps5(ctx, HE_K_MAC);
-        if ((e = ps5.done(launch_mac_full(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, ctx->lc, st, ps5.ev()))) != hipSuccess)
+        e = (B >= 4) ? launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, false, ctx->lc, st,
+                                        ps5.ev())
+                     : launch_mac_full(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, ctx->lc, st, ps5.ev());
+        if ((e = ps5.done(e)) != hipSuccess)
             return dev_fail(e, "conv mac");
         EpiParams ep;
         std::memset(&ep, 0, sizeof(ep));

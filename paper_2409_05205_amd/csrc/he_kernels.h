@@ -69,6 +69,11 @@ hipError_t launch_mac_class(const uint32_t *X, const uint32_t *Op, uint32_t *h, 
                             uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s,
                             const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
 
+// Batched MAC, register-blocked over 4 images x 4 channels per thread (either form).
+hipError_t launch_mac_tiled(const uint32_t *X, const uint32_t *Op, uint32_t *out, uint32_t B, uint32_t Jtot,
+                            uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool class_form,
+                            const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
+
 // Inverse transform of size N/s of each channel's folded vector, scattered to its residue
 // class of the output poly, plus Delta sh'.  One workgroup per (b, g, l).
 hipError_t launch_tail_class(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B,

@@ -102,6 +102,102 @@ k_mac_class(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uin
     }
 }
 
+// ------------------------------------------------------------------ batched MAC
+// Register-blocked over images and channels: one thread owns two consecutive
+// slots for a tile of IB images x NB channels (IB*NB*2 64-bit accumulators),
+// so each loaded input word feeds NB products and each operand word IB.  A
+// workgroup covers 512 slots of one limb; the IB x NB tiles of one (limb,
+// 512-slot) slice all run on the same XCD (workgroup ids are dealt to the 8
+// XCDs round robin), so that slice of inputs and operands is read from HBM
+// about once and then served by that XCD's L2.
+constexpr int TB_IB = 4, TB_NB = 4, TB_THREADS = 256, TB_SLOTS = 2 * TB_THREADS;
+
+template <bool CLASS>
+__global__ void __launch_bounds__(TB_THREADS)
+k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ out, uint32_t B,
+            uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s_log, uint32_t n_super,
+            uint32_t tiles_b, uint32_t tiles_n, LimbConsts lc) {
+    const uint32_t w = blockIdx.x;
+    const uint32_t xcd = w & 7u;
+    const uint32_t r = w >> 3;
+    const uint32_t per = tiles_b * tiles_n;
+    const uint32_t t = r % per;
+    const uint32_t S = (r / per) * 8u + xcd;          // (limb, slot chunk) slice
+    if (S >= n_super) return;                          // whole workgroup: no shuffles skipped
+    const uint32_t chunks = (N + TB_SLOTS - 1) / TB_SLOTS;
+    const uint32_t l = S / chunks;
+    const uint32_t k2 = (S % chunks) * TB_SLOTS + threadIdx.x * 2u;
+    const bool live = k2 < N;
+    const uint32_t b0 = (t / tiles_n) * TB_IB;
+    const uint32_t n0 = (t % tiles_n) * TB_NB;
+    const LimbConst c = lc.l[l];
+    uint64_t acc[TB_IB][TB_NB][2];
+#pragma unroll
+    for (int i = 0; i < TB_IB; ++i)
+#pragma unroll
+        for (int j = 0; j < TB_NB; ++j) acc[i][j][0] = acc[i][j][1] = 0;
+    if (live) {
+        const uint32_t *xp[TB_IB];
+        const uint32_t *op[TB_NB];
+#pragma unroll
+        for (int i = 0; i < TB_IB; ++i) {
+            const uint32_t b = min(b0 + i, B - 1);
+            xp[i] = X + ((size_t)b * Jtot * L + l) * N + k2;
+        }
+#pragma unroll
+        for (int j = 0; j < TB_NB; ++j) {
+            const uint32_t n = min(n0 + j, c_o - 1);
+            op[j] = Op + (size_t)(n * L + l) * Jtot * N + k2;
+        }
+        const size_t xs = (size_t)L * N;
+        uint32_t cnt = 0;
+        for (uint32_t J = 0; J < Juse; ++J) {
+            uint2 xv[TB_IB], ov[TB_NB];
+#pragma unroll
+            for (int i = 0; i < TB_IB; ++i) xv[i] = *reinterpret_cast<const uint2 *>(xp[i] + J * xs);
+#pragma unroll
+            for (int j = 0; j < TB_NB; ++j) ov[j] = *reinterpret_cast<const uint2 *>(op[j] + (size_t)J * N);
+#pragma unroll
+            for (int i = 0; i < TB_IB; ++i)
+#pragma unroll
+                for (int j = 0; j < TB_NB; ++j) {
+                    acc[i][j][0] += (uint64_t)xv[i].x * ov[j].x;
+                    acc[i][j][1] += (uint64_t)xv[i].y * ov[j].y;
+                }
+            if (++cnt == 15) {
+#pragma unroll
+                for (int i = 0; i < TB_IB; ++i)
+#pragma unroll
+                    for (int j = 0; j < TB_NB; ++j) {
+                        acc[i][j][0] = reduce64(acc[i][j][0], c);
+                        acc[i][j][1] = reduce64(acc[i][j][1], c);
+                    }
+                cnt = 0;
+            }
+        }
+    }
+    const uint32_t s = 1u << s_log;
+    const uint32_t M = CLASS ? (N >> s_log) : N;
+#pragma unroll
+    for (int i = 0; i < TB_IB; ++i)
+#pragma unroll
+        for (int j = 0; j < TB_NB; ++j) {
+            const uint32_t r0 = reduce64(acc[i][j][0], c);
+            const uint32_t r1 = reduce64(acc[i][j][1], c);
+            const uint32_t b = b0 + i, n = n0 + j;
+            const bool mine = live && b < B && n < c_o;
+            uint32_t *dst = out + ((size_t)(b * c_o + n) * L + l) * M;
+            if (!CLASS || s == 1) {
+                if (mine) *reinterpret_cast<uint2 *>(dst + k2) = make_uint2(r0, r1);
+            } else {
+                uint32_t v = addmod(r0, r1, c.q);
+                const uint32_t lanes = s >> 1;          // lanes per block (<= 64)
+                for (uint32_t m = 1; m < lanes; m <<= 1) v = addmod(v, (uint32_t)__shfl_xor((int)v, (int)m), c.q);
+                if (mine && (threadIdx.x & (lanes - 1)) == 0) dst[k2 >> s_log] = v;
+            }
+        }
+}
+
 __device__ __forceinline__ uint32_t mul_delta(uint32_t m, const LimbConst &c) {
     return csub(shoup_lazy(m, c.delta, c.delta_sh, c.q), c.q);
 }
@@ -278,5 +374,26 @@ hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *
                                 uint32_t N, const LimbConsts &lc, hipStream_t st) {
     dim3 grid((N + 255) / 256, rows * L);
     hipLaunchKernelGGL(k_pointwise, grid, dim3(256), 0, st, a, b, c, L, N, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_mac_tiled(const uint32_t *X, const uint32_t *Op, uint32_t *out, uint32_t B, uint32_t Jtot,
+                            uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool class_form,
+                            const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
+    if (B == 0) return hipSuccess;
+    uint32_t s_log = 0;
+    while ((1u << s_log) < s) ++s_log;
+    if (class_form && s > 2 * 64) return hipErrorInvalidValue;   // s/2 lanes must fit one wave
+    const uint32_t chunks = (N + TB_SLOTS - 1) / TB_SLOTS;
+    const uint32_t n_super = chunks * L;
+    const uint32_t tiles_b = (B + TB_IB - 1) / TB_IB;
+    const uint32_t tiles_n = (c_o + TB_NB - 1) / TB_NB;
+    const uint32_t grid = ((n_super + 7) / 8) * 8 * tiles_b * tiles_n;
+    if (class_form)
+        HE_LAUNCH(ev, k_mac_tiled<true>, dim3(grid), dim3(TB_THREADS), 0, st, X, Op, out, B, Jtot, Juse, c_o, L, N,
+                  s_log, n_super, tiles_b, tiles_n, lc);
+    else
+        HE_LAUNCH(ev, k_mac_tiled<false>, dim3(grid), dim3(TB_THREADS), 0, st, X, Op, out, B, Jtot, Juse, c_o, L, N,
+                  s_log, n_super, tiles_b, tiles_n, lc);
     return hipGetLastError();
 }

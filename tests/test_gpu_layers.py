@@ -161,3 +161,34 @@ def test_empty_batch_is_noop(he):
     c0 = torch.zeros((0, 1, L, N), dtype=torch.int32, device="cuda:0")
     out = ctx.conv_layer(layer, c0)
     assert out.shape == (0, layer.K_out, L, N)
+
+
+BATCHED_FULL = [(16, 16, 32, 1), (32, 32, 16, 1), (64, 64, 8, 1), (16, 32, 32, 2)]
+
+
+@pytest.mark.parametrize("c_i,c_o,H,stride", BATCHED_FULL)
+@pytest.mark.parametrize("flags", [0, 1])
+def test_batched_fullsize_layer(he, c_i, c_o, H, stride, flags):
+    """B = 6 images at N = 8192, 4 limbs (register-blocked MAC, ragged image tile):
+    sampled images bit-exact vs the oracle, every image equal to its single-image call."""
+    N, L = 8192, 4
+    ctx = he.Context(N, L, T)
+    octx = bfv.make_ctx(N, L, T)
+    g = packing.conv_geometry(N, c_i, c_o, H, H, 3, stride, 1)
+    rng = np.random.default_rng(c_i * 100 + c_o + H + flags)
+    F = rng.integers(-7, 8, (c_o, c_i, 3, 3))
+    rho = rng.integers(0, T, (g.K_in, c_o, N))
+    from paper_2409_05205_amd import he as h
+    layer = ctx.pack_conv(h.ConvSpec(c_i, c_o, H, H, 3, stride, 1), F, rho, flags)
+    B = 6
+    c0 = np.stack([wl.uniform_per_modulus(rng, (g.K_in,), octx.primes, N) for _ in range(B)])
+    sh = rng.integers(0, T, (B, g.K_in, N))
+    shn = rng.integers(0, T, (B, g.K_out, N))
+    got = host(ctx.conv_layer(layer, dev(c0), dev(sh), dev(shn)))
+    fh = packing.pack_conv_filters(F, g)
+    for b in (0, B - 1):
+        want = bfv.server_conv(octx, g, c0[b].astype(np.uint64), rho, fh, sh[b], shn[b])
+        assert (got[b] == want).all(), f"image {b}"
+    for b in range(B):
+        alone = host(ctx.conv_layer(layer, dev(c0[b:b + 1]), dev(sh[b:b + 1]), dev(shn[b:b + 1])))
+        assert (alone[0] == got[b]).all(), f"image {b} alone"
