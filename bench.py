@@ -172,6 +172,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=6000)
+    ap.add_argument("--served-warmup", type=int, default=500)
+    ap.add_argument("--served-rate", type=float, default=2000.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -307,6 +311,41 @@ def main():
             torch.cuda.empty_cache()
         bres["all_widths_layers_per_s"] = round(tot_layers / tot_time, 1)
         result["forms"]["batched"] = bres
+
+    # ---------------- served: Poisson stream of single-layer requests, 128 clients
+    if not args.no_served:
+        from paper_2409_05205_amd import serve
+        log("setup: served variants x1/x2 (N=8192, 10 classes), x4 (N=16384, 100 classes), 128 clients")
+        ctx16 = he.Context(16384, 6, wl.T_PLAIN)
+        variants = [serve.pack_variant(1, 10, ctx), serve.pack_variant(2, 10, ctx), serve.pack_variant(4, 100, ctx16)]
+        clients = 128
+        buffers = [serve.client_buffers(v, clients, seed=v.width) for v in variants]
+        sync()
+        n_types = sum(len(v.layers) for v in variants)
+        n = args.served_requests + args.served_warmup
+        arrival, ltype, client = serve.poisson_trace(args.served_rate, n, n_types, clients, seed=1)
+        sres = {"offered_req_per_s": args.served_rate, "clients": clients, "layer_types": n_types,
+                "requests": args.served_requests, "warmup_requests": args.served_warmup}
+        budget = 8 << 30
+        for name, streams, mb in [("served", 4, 8), ("plain_fcfs", 1, 1)]:
+            res = serve.run_trace(variants, buffers, arrival, ltype, client, streams, mb, budget, timeout_s=300)
+            st = serve.latency_stats(res, args.served_warmup)
+            st.update({"streams": streams, "max_batch": mb, "rc": res["rc"]})
+            sres[name] = st
+            log(f"{name}: {json.dumps(st)}")
+        # capacity: the whole trace arrives at once
+        sat_n = min(3000, n)
+        z = np.zeros(sat_n)
+        for name, streams, mb in [("served_saturated", 4, 8), ("plain_saturated", 1, 1)]:
+            res = serve.run_trace(variants, buffers, z, ltype[:sat_n], client[:sat_n], streams, mb, budget,
+                                  timeout_s=300)
+            span = res["complete"].max()
+            sres[name] = {"requests": sat_n, "layers_per_s": sat_n / span, "mean_batch": float(res["batch"].mean()),
+                          "rc": res["rc"]}
+            log(f"{name}: {json.dumps(sres[name])}")
+        result["forms"]["served"] = sres
+        del variants, buffers
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -208,6 +208,43 @@ int he_seq_replay(he_seq *seq, void *stream);
 uint32_t he_seq_length(const he_seq *seq);
 void he_seq_free(he_seq *seq);
 
+/*
+ * Serving runtime: continuous batching of layer requests (the server of Alg. 1
+ * / Alg. 2 answering many clients).  Layers are registered once; a request
+ * names a layer, its arrival time in seconds from the start of the run, and
+ * resident device buffers laid out as for one image of he_conv_layer /
+ * he_fc_layer (d_sh / d_sh_next may be NULL as there).  he_server_run replays
+ * the time-ordered trace in real time: a generator thread submits each request
+ * at its arrival time and a dispatcher thread admits the oldest pending
+ * request whenever one of `streams` stream slots is free and its transient
+ * memory (workspace, plus gather / scatter staging when batched) fits in the
+ * free part of an hbm_budget_bytes pool allocated at creation; up to max_batch
+ * pending requests of the same layer (and the same share pattern) ride along.
+ * Batches on different slots run concurrently.  A request whose memory can
+ * never fit fails with HE_ENOMEM; a request whose batch reports a device error
+ * fails with HE_EDEVICE; timeout_s > 0 bounds the run.  Every request's output
+ * words equal those of a lone layer call on its inputs.  streams = 1 and
+ * max_batch = 1 give the plain first-come first-served one-request-per-launch
+ * server.  Results: per request arrival, dispatch and completion times
+ * (seconds), batch size and status.
+ */
+typedef struct he_server he_server;
+typedef struct {
+    uint32_t streams;            /* concurrent stream slots, 1..64                  */
+    uint32_t max_batch;          /* requests of one layer per launch, 1..1024       */
+    uint64_t hbm_budget_bytes;   /* pool for transient per-batch device memory      */
+    double timeout_s;            /* abandon the run after this long (0: no limit)   */
+} he_server_config;
+int he_server_create(const he_server_config *cfg, he_server **out);
+int he_server_add_layer(he_server *srv, he_ctx *ctx, const he_layer *layer, uint32_t *layer_id);
+int he_server_add_request(he_server *srv, uint32_t layer_id, double arrival_s, const uint32_t *d_c0,
+                          const uint32_t *d_sh, const uint32_t *d_sh_next, uint32_t *d_out);
+int he_server_run(he_server *srv);
+uint32_t he_server_requests(const he_server *srv);
+int he_server_results(const he_server *srv, double *arrival, double *dispatch, double *complete,
+                      uint32_t *batch, int32_t *status);
+void he_server_free(he_server *srv);
+
 void he_free_layer(he_layer *layer);
 void he_free(he_ctx *ctx);
 const char *he_strerror(int code);

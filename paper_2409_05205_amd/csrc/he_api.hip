@@ -563,7 +563,7 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
     const uint32_t Juse = d_sh ? Jtot : K_in;
     if (in.flags == HE_PACK_CLASS_INTT) {
         ProfScope ps3(ctx, HE_K_MAC);
-        e = (B >= 4 && in.s <= 128)
+        e = (B >= 4 && in.s >= 2 && in.s <= 128)
                 ? launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, true, ctx->lc, st, ps3.ev())
                 : launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, ctx->lc, st, ps3.ev());
         if ((e = ps3.done(e)) != hipSuccess)

@@ -117,6 +117,10 @@ __global__ void __launch_bounds__(TB_THREADS)
 k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ out, uint32_t B,
             uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s_log, uint32_t n_super,
             uint32_t tiles_b, uint32_t tiles_n, LimbConsts lc) {
+    // In the residue-class form with s >= 2 the thread's two slots lie in one block
+    // and are summed into one accumulator (two products per input row J, folded
+    // every 7 rows); otherwise each slot keeps its own accumulator (folded every 15).
+    constexpr int NS = CLASS ? 1 : 2;
     const uint32_t w = blockIdx.x;
     const uint32_t xcd = w & 7u;
     const uint32_t r = w >> 3;
@@ -131,11 +135,13 @@ k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uin
     const uint32_t b0 = (t / tiles_n) * TB_IB;
     const uint32_t n0 = (t % tiles_n) * TB_NB;
     const LimbConst c = lc.l[l];
-    uint64_t acc[TB_IB][TB_NB][2];
+    uint64_t acc[TB_IB][TB_NB][NS];
 #pragma unroll
     for (int i = 0; i < TB_IB; ++i)
 #pragma unroll
-        for (int j = 0; j < TB_NB; ++j) acc[i][j][0] = acc[i][j][1] = 0;
+        for (int j = 0; j < TB_NB; ++j)
+#pragma unroll
+            for (int u = 0; u < NS; ++u) acc[i][j][u] = 0;
     if (live) {
         const uint32_t *xp[TB_IB];
         const uint32_t *op[TB_NB];
@@ -150,6 +156,7 @@ k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uin
             op[j] = Op + (size_t)(n * L + l) * Jtot * N + k2;
         }
         const size_t xs = (size_t)L * N;
+        const uint32_t fold = CLASS ? 7u : 15u;
         uint32_t cnt = 0;
         for (uint32_t J = 0; J < Juse; ++J) {
             uint2 xv[TB_IB], ov[TB_NB];
@@ -161,37 +168,40 @@ k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uin
             for (int i = 0; i < TB_IB; ++i)
 #pragma unroll
                 for (int j = 0; j < TB_NB; ++j) {
-                    acc[i][j][0] += (uint64_t)xv[i].x * ov[j].x;
-                    acc[i][j][1] += (uint64_t)xv[i].y * ov[j].y;
+                    if (CLASS) {
+                        acc[i][j][0] += (uint64_t)xv[i].x * ov[j].x;
+                        acc[i][j][0] += (uint64_t)xv[i].y * ov[j].y;
+                    } else {
+                        acc[i][j][0] += (uint64_t)xv[i].x * ov[j].x;
+                        acc[i][j][NS - 1] += (uint64_t)xv[i].y * ov[j].y;
+                    }
                 }
-            if (++cnt == 15) {
+            if (++cnt == fold) {
 #pragma unroll
                 for (int i = 0; i < TB_IB; ++i)
 #pragma unroll
-                    for (int j = 0; j < TB_NB; ++j) {
-                        acc[i][j][0] = reduce64(acc[i][j][0], c);
-                        acc[i][j][1] = reduce64(acc[i][j][1], c);
-                    }
+                    for (int j = 0; j < TB_NB; ++j)
+#pragma unroll
+                        for (int u = 0; u < NS; ++u) acc[i][j][u] = reduce64(acc[i][j][u], c);
                 cnt = 0;
             }
         }
     }
-    const uint32_t s = 1u << s_log;
     const uint32_t M = CLASS ? (N >> s_log) : N;
 #pragma unroll
     for (int i = 0; i < TB_IB; ++i)
 #pragma unroll
         for (int j = 0; j < TB_NB; ++j) {
-            const uint32_t r0 = reduce64(acc[i][j][0], c);
-            const uint32_t r1 = reduce64(acc[i][j][1], c);
             const uint32_t b = b0 + i, n = n0 + j;
             const bool mine = live && b < B && n < c_o;
             uint32_t *dst = out + ((size_t)(b * c_o + n) * L + l) * M;
-            if (!CLASS || s == 1) {
-                if (mine) *reinterpret_cast<uint2 *>(dst + k2) = make_uint2(r0, r1);
+            if (!CLASS) {
+                if (mine)
+                    *reinterpret_cast<uint2 *>(dst + k2) =
+                        make_uint2(reduce64(acc[i][j][0], c), reduce64(acc[i][j][NS - 1], c));
             } else {
-                uint32_t v = addmod(r0, r1, c.q);
-                const uint32_t lanes = s >> 1;          // lanes per block (<= 64)
+                uint32_t v = reduce64(acc[i][j][0], c);
+                const uint32_t lanes = (1u << s_log) >> 1;   // lanes per block (<= 64)
                 for (uint32_t m = 1; m < lanes; m <<= 1) v = addmod(v, (uint32_t)__shfl_xor((int)v, (int)m), c.q);
                 if (mine && (threadIdx.x & (lanes - 1)) == 0) dst[k2 >> s_log] = v;
             }
@@ -261,8 +271,8 @@ k_tail_class(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const u
 }
 
 // ------------------------------------------------------------------ pack-time kernels
-__device__ __forceinline__ uint32_t mulmod_slow(uint32_t a, uint32_t b, uint32_t q) {
-    return (uint32_t)(((uint64_t)a * b) % q);
+__device__ __forceinline__ uint32_t mulmod_c(uint32_t a, uint32_t b, const LimbConst &c) {
+    return reduce64((uint64_t)a * b, c);
 }
 
 __global__ void k_expand(const uint32_t *__restrict__ rho, const int16_t *__restrict__ fhat, uint32_t *__restrict__ Op,
@@ -280,7 +290,7 @@ __global__ void k_expand(const uint32_t *__restrict__ rho, const int16_t *__rest
         v = rho[((size_t)J * c_o + n) * N + k];
     } else {
         const int32_t f = fhat[((size_t)(J - K_in) * c_o + n) * N + k];
-        const uint32_t a = mulmod_slow((uint32_t)(f < 0 ? -f : f), c.delta, c.q);
+        const uint32_t a = mulmod_c((uint32_t)(f < 0 ? -f : f), c.delta, c);
         // -Delta f mod q
         v = (f > 0) ? (a == 0 ? 0u : c.q - a) : a;
     }
@@ -301,13 +311,13 @@ __global__ void k_scale(uint32_t *__restrict__ Op, const uint32_t *__restrict__ 
         uint32_t base = xinv[(size_t)l * N + k];
         uint32_t p = 1;
         while (e) {
-            if (e & 1) p = mulmod_slow(p, base, c.q);
-            base = mulmod_slow(base, base, c.q);
+            if (e & 1) p = mulmod_c(p, base, c);
+            base = mulmod_c(base, base, c);
             e >>= 1;
         }
-        fac = mulmod_slow(fac, p, c.q);
+        fac = mulmod_c(fac, p, c);
     }
-    Op[(size_t)row * N + k] = mulmod_slow(Op[(size_t)row * N + k], fac, c.q);
+    Op[(size_t)row * N + k] = mulmod_c(Op[(size_t)row * N + k], fac, c);
 }
 
 __global__ void k_pointwise(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b, uint32_t *__restrict__ cc,
@@ -383,7 +393,7 @@ hipError_t launch_mac_tiled(const uint32_t *X, const uint32_t *Op, uint32_t *out
     if (B == 0) return hipSuccess;
     uint32_t s_log = 0;
     while ((1u << s_log) < s) ++s_log;
-    if (class_form && s > 2 * 64) return hipErrorInvalidValue;   // s/2 lanes must fit one wave
+    if (class_form && (s < 2 || s > 2 * 64)) return hipErrorInvalidValue;   // one block spans 1..64 lanes
     const uint32_t chunks = (N + TB_SLOTS - 1) / TB_SLOTS;
     const uint32_t n_super = chunks * L;
     const uint32_t tiles_b = (B + TB_IB - 1) / TB_IB;

@@ -367,19 +367,19 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
         for (int i = 0; i < (1 << LOGR); ++i) my[lpad(inv_final_idx<LOGM, LOGR>(t, i))] = csub(v[i], c.q);
     }
     __syncthreads();
-    const uint32_t s = 1u << s_log;
-    const uint32_t cls_w = s / g_o;
-    const uint32_t span = RW * cls_w;
-    const uint32_t c_lo = np0 * cls_w;
+    // g_o, RW and s are powers of two: class width, span and indices by shifts
+    const uint32_t cw_log = s_log - (31u - __clz(g_o));
+    const uint32_t span_log = (31u - __clz(RW)) + cw_log;
+    const uint32_t c_lo = np0 << cw_log;
     uint32_t *o = out + ((size_t)(b * K_out + g) * L + l) * N;
     const uint32_t *sh = sh_next ? sh_next + (size_t)(b * K_out + g) * N : nullptr;
-    const uint32_t total = span * M;
+    const uint32_t total = (uint32_t)M << span_log;
     for (uint32_t e = tid; e < total; e += blockDim.x) {
-        const uint32_t m = e / span;
-        const uint32_t off = e - m * span;
-        const uint32_t r = off / cls_w;
+        const uint32_t m = e >> span_log;
+        const uint32_t off = e & ((1u << span_log) - 1u);
+        const uint32_t r = off >> cw_log;
         uint32_t val = 0;
-        if (off - r * cls_w == 0 && g * g_o + np0 + r < c_o) val = lds[r * MP + lpad(m)];
+        if ((off & ((1u << cw_log) - 1u)) == 0 && g * g_o + np0 + r < c_o) val = lds[r * MP + lpad(m)];
         const uint32_t k = (m << s_log) + c_lo + off;
         if (sh) val = csub(val + mul_delta_msg(sh[k], c), c.q);
         o[k] = val;

@@ -29,6 +29,8 @@ EXPORTED = [
     "he_profile_enable", "he_profile_read", "he_profile_reset",
     "he_seq_create", "he_seq_add", "he_seq_run", "he_seq_capture", "he_seq_replay", "he_seq_length",
     "he_seq_free",
+    "he_server_create", "he_server_add_layer", "he_server_add_request", "he_server_run", "he_server_requests",
+    "he_server_results", "he_server_free",
 ]
 HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT = 1, 2, 4, 8
 
@@ -44,6 +46,11 @@ class LayerDesc(ctypes.Structure):
                 ("H", ctypes.c_uint32), ("W", ctypes.c_uint32), ("f", ctypes.c_uint32),
                 ("stride", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("n_i", ctypes.c_uint32),
                 ("n_o", ctypes.c_uint32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("timeout_s", ctypes.c_double)]
 
 
 class LayerInfo(ctypes.Structure):
@@ -94,6 +101,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_seq_length.argtypes = [VP]
     lib.he_seq_length.restype = U32
     lib.he_seq_free.argtypes = [VP]
+    lib.he_server_create.argtypes = [P(ServerConfig), P(VP)]
+    lib.he_server_add_layer.argtypes = [VP, VP, VP, P(U32)]
+    lib.he_server_add_request.argtypes = [VP, U32, ctypes.c_double, VP, VP, VP, VP]
+    lib.he_server_run.argtypes = [VP]
+    lib.he_server_requests.argtypes = [VP]
+    lib.he_server_requests.restype = U32
+    D = P(ctypes.c_double)
+    lib.he_server_results.argtypes = [VP, D, D, D, P(U32), P(ctypes.c_int32)]
+    lib.he_server_free.argtypes = [VP]
     lib.he_free_layer.argtypes = [VP]
     lib.he_free.argtypes = [VP]
     lib.he_strerror.argtypes = [ctypes.c_int]
@@ -101,7 +117,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name not in ("he_layer_workspace_bytes", "he_strerror", "he_last_error", "he_free", "he_free_layer",
-                        "he_seq_length", "he_seq_free"):
+                        "he_seq_length", "he_seq_free", "he_server_requests", "he_server_free"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -384,6 +400,62 @@ class Sequence:
     def free(self):
         if getattr(self, "handle", None):
             load_library().he_seq_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """he_server_*: continuous-batching server replaying a trace of layer requests."""
+
+    def __init__(self, streams: int = 4, max_batch: int = 8, hbm_budget_bytes: int = 4 << 30,
+                 timeout_s: float = 0.0):
+        cfg = ServerConfig(streams, max_batch, hbm_budget_bytes, timeout_s)
+        h = ctypes.c_void_p()
+        _check(load_library().he_server_create(ctypes.byref(cfg), ctypes.byref(h)), "he_server_create")
+        self.handle = h
+        self._keep = []
+
+    def add_layer(self, ctx: Context, layer: Layer) -> int:
+        lid = ctypes.c_uint32()
+        _check(load_library().he_server_add_layer(self.handle, ctx.handle, layer.handle, ctypes.byref(lid)),
+               "he_server_add_layer")
+        self._keep.append((ctx, layer))
+        return int(lid.value)
+
+    def add_request(self, layer_id: int, arrival_s: float, c0, sh, sh_next, out) -> None:
+        """Buffers: one image's worth, laid out as for he_conv_layer / he_fc_layer (contiguous views)."""
+        for name, t in (("c0", c0), ("out", out)):
+            if t is None or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous device tensor")
+        _check(load_library().he_server_add_request(self.handle, layer_id, float(arrival_s), _ptr(c0), _ptr(sh),
+                                                    _ptr(sh_next), _ptr(out)), "he_server_add_request")
+
+    def run(self) -> int:
+        """Replay the trace; returns the first error code (0 when every request succeeded)."""
+        return int(load_library().he_server_run(self.handle))
+
+    def results(self):
+        n = int(load_library().he_server_requests(self.handle))
+        arr = np.zeros(n)
+        dis = np.zeros(n)
+        com = np.zeros(n)
+        bat = np.zeros(n, dtype=np.uint32)
+        st = np.zeros(n, dtype=np.int32)
+        D = ctypes.POINTER(ctypes.c_double)
+        _check(load_library().he_server_results(
+            self.handle, arr.ctypes.data_as(D), dis.ctypes.data_as(D), com.ctypes.data_as(D),
+            bat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+            "he_server_results")
+        return dict(arrival=arr, dispatch=dis, complete=com, batch=bat, status=st)
+
+    def free(self):
+        if getattr(self, "handle", None):
+            load_library().he_server_free(self.handle)
             self.handle = None
 
     def __del__(self):

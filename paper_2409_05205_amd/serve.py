@@ -1,0 +1,144 @@
+"""Served form: many clients streaming single-layer requests to one GPU.
+
+Builds the packed plain-20 variants (the server's resident NTT-domain operands),
+per-client resident ciphertext buffers for every layer, a Poisson arrival trace
+in which each request names a uniformly random client and layer type, and
+replays it through the native continuous-batching server (he_server_*).  The
+same trace replayed with one stream and batch 1 is the plain first-come
+first-served one-request-per-launch server it is compared against.
+
+Per-client inputs are synthetic: c0 shares uniform per limb (what RLWE
+ciphertexts look like to the server), shares uniform in [0, t), drawn on the
+device from a seeded generator per (variant, layer).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+import workloads as wl
+
+from . import he
+
+
+@dataclass
+class Variant:
+    """One packed plain-20 width variant on its own ring."""
+    width: int
+    classes: int
+    ctx: "he.Context"
+    shapes: List[object]
+    layers: List["he.Layer"] = field(default_factory=list)
+
+
+def pack_variant(width: int, classes: int, ctx: "he.Context", cfg: int = wl.CONFIG_SERVED) -> Variant:
+    v = Variant(width, classes, ctx, wl.plain20(width, classes))
+    N = ctx.N
+    for k, shp in enumerate(v.shapes):
+        W = wl.layer_weights(cfg, width, k, shp)
+        if shp.kind == "conv":
+            spec = he.ConvSpec(shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
+            til = ctx.conv_tiling(spec)
+            rho = wl.mask_polys(cfg, width, k, til["K_in"] * shp.c_o, N).reshape(til["K_in"], shp.c_o, N)
+            v.layers.append(ctx.pack_conv(spec, W, rho))
+        else:
+            nop = 1 << (shp.n_o - 1).bit_length()
+            if shp.n_i * nop > N:
+                nop = 1 << ((N // shp.n_i).bit_length() - 1)
+            blocks = -(-shp.n_o // nop)
+            rho = wl.mask_polys(cfg, width, k, blocks, N)
+            v.layers.append(ctx.pack_fc(he.FCSpec(shp.n_i, shp.n_o), W, rho, wl.layer_bias(cfg, width, k, shp)))
+    return v
+
+
+def _uniform_limbs(shape_lead, primes, N, gen, device):
+    import torch
+    L = len(primes)
+    out = torch.empty(tuple(shape_lead) + (L, N), dtype=torch.int32, device=device)
+    for l, q in enumerate(primes):
+        out[..., l, :] = torch.randint(0, int(q), tuple(shape_lead) + (N,), generator=gen, device=device,
+                                       dtype=torch.int32)
+    return out
+
+
+@dataclass
+class LayerBuffers:
+    c0: object
+    sh: Optional[object]
+    shn: Optional[object]
+    out: object
+
+
+def client_buffers(v: Variant, clients: int, seed: int, device="cuda:0") -> List[LayerBuffers]:
+    """Resident per-client inputs and outputs of every layer of a variant: tensors [clients][...]."""
+    import torch
+    bufs = []
+    ctx = v.ctx
+    N, L, t = ctx.N, ctx.L, ctx.t
+    for k, (shp, ly) in enumerate(zip(v.shapes, v.layers)):
+        g = torch.Generator(device=device)
+        g.manual_seed(seed * 1000003 + v.width * 101 + k)
+        first, last = k == 0, k == len(v.shapes) - 1
+        i = ly.info
+        if shp.kind == "conv":
+            c0 = _uniform_limbs((clients, i.K_in), ctx.primes, N, g, device)
+            sh = None if first else torch.randint(0, t, (clients, i.K_in, N), generator=g, device=device,
+                                                 dtype=torch.int32)
+            shn = None if last else torch.randint(0, t, (clients, i.K_out, N), generator=g, device=device,
+                                                 dtype=torch.int32)
+            out = torch.empty((clients, i.K_out, L, N), dtype=torch.int32, device=device)
+        else:
+            c0 = _uniform_limbs((clients,), ctx.primes, N, g, device)
+            sh = torch.randint(0, t, (clients, N), generator=g, device=device, dtype=torch.int32)
+            shn = None if last else torch.randint(0, t, (clients, i.blocks, i.n_o_p), generator=g, device=device,
+                                                 dtype=torch.int32)
+            out = torch.empty((clients, i.blocks, L, i.n_o_p), dtype=torch.int32, device=device)
+        bufs.append(LayerBuffers(c0, sh, shn, out))
+    return bufs
+
+
+def poisson_trace(rate: float, n: int, layer_types: int, clients: int, seed: int):
+    """Arrival times (s), layer-type index and client index of n requests."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([wl.MASTER_SEED, wl.CONFIG_SERVED, seed])))
+    gaps = rng.exponential(1.0 / rate, n)
+    arrival = np.cumsum(gaps) - gaps[0]
+    return arrival, rng.integers(0, layer_types, n), rng.integers(0, clients, n)
+
+
+def run_trace(variants: List[Variant], buffers: List[List[LayerBuffers]], arrival, ltype, client,
+              streams: int, max_batch: int, budget: int, timeout_s: float = 0.0):
+    """Replay a trace through he_server; returns the server's per-request results and the type table."""
+    srv = he.Server(streams, max_batch, budget, timeout_s)
+    table = []      # layer-type index -> (variant index, layer index, server layer id)
+    for vi, v in enumerate(variants):
+        for k, ly in enumerate(v.layers):
+            table.append((vi, k, srv.add_layer(v.ctx, ly)))
+    for a, lt, cl in zip(arrival, ltype, client):
+        vi, k, lid = table[int(lt)]
+        b = buffers[vi][k]
+        srv.add_request(lid, float(a), b.c0[cl], None if b.sh is None else b.sh[cl],
+                        None if b.shn is None else b.shn[cl], b.out[cl])
+    rc = srv.run()
+    res = srv.results()
+    srv.free()
+    res["rc"] = rc
+    return res
+
+
+def latency_stats(res, warmup: int):
+    lat = (res["complete"] - res["arrival"])[warmup:]
+    ok = res["status"][warmup:] == 0
+    a = res["arrival"][warmup:]
+    c = res["complete"][warmup:]
+    span = c.max() - a.min() if len(a) else float("nan")
+    return {
+        "requests": int(len(lat)),
+        "failed": int((~ok).sum()),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3),
+        "layers_per_s": float(len(lat) / span),
+        "mean_batch": float(res["batch"][warmup:].mean()),
+    }
