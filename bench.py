@@ -94,6 +94,11 @@ class Stack:
         for ly, B, c0, sh, shn in self.steps:
             self.seq.add(ly, c0, sh, shn)
 
+    def autotune(self):
+        """Time every kernel variant on each layer's launch shapes; keep the fastest."""
+        for ly, B, c0, sh, shn in self.steps:
+            self.ctx.autotune(ly, B)
+
     def image_layers(self):
         """Image-layer evaluations per pass (conv layers count B images, FC heads their B)."""
         return sum(B for _, B, _, _, _ in self.steps)
@@ -177,6 +182,7 @@ def main():
     ap.add_argument("--served-warmup", type=int, default=500)
     ap.add_argument("--served-rate", type=float, default=2000.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards across GPUs by "
@@ -196,6 +202,8 @@ def main():
     ctx = he.Context(8192, 4, wl.T_PLAIN)
     st = Stack(he, ctx, wl.CONFIG_PLAIN20_X1, 1, [10], [1], 8192, 4)
     n_layers = len(st.steps)
+    if not args.no_tune:
+        st.autotune()
     sync()
 
     # plain: native runtime, one image, 20 calls back to back
@@ -292,6 +300,8 @@ def main():
             log(f"setup: batched x{width} N={N} L={L}")
             bctx = ctx if N == 8192 else he.Context(N, L, wl.T_PLAIN)
             bst = Stack(he, bctx, wl.CONFIG_BATCHED, width, [10, 100], [32, 32], N, L)
+            if not args.no_tune:
+                bst.autotune()
             sync()
             bseq = he.Sequence(bctx)
             for ly, B, c0, sh, shn in bst.steps:

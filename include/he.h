@@ -245,6 +245,22 @@ int he_server_results(const he_server *srv, double *arrival, double *dispatch, d
                       uint32_t *batch, int32_t *status);
 void he_server_free(he_server *srv);
 
+/*
+ * Tuning.  Knobs: HE_TUNE_NTT_FWD / HE_TUNE_NTT_INV / HE_TUNE_TAIL take the
+ * register radix log2 r in 2..5 (each thread keeps 2^r words and runs r stages
+ * per LDS pass; 0 = automatic), HE_TUNE_MAC takes 0 (streaming per-image MAC),
+ * 1 (register-blocked batched MAC) or -1 (automatic).  Every value yields the
+ * same output words.  he_tune_force pins a knob for the whole context (tests
+ * sweep all values with it).  he_autotune_layer times every candidate of every
+ * knob on the launch shapes of one layer at batch B (synchronising the stream)
+ * and keeps the fastest for later calls with that shape; he_tune_get reads a
+ * kept choice back (key: knob, log2 of the transform size, rows per launch).
+ */
+enum { HE_TUNE_NTT_FWD = 1, HE_TUNE_NTT_INV = 2, HE_TUNE_TAIL = 3, HE_TUNE_MAC = 4 };
+int he_tune_force(he_ctx *ctx, uint32_t knob, int32_t value);
+int he_autotune_layer(he_ctx *ctx, const he_layer *layer, uint32_t B, void *stream);
+int he_tune_get(he_ctx *ctx, uint32_t knob, uint32_t key_size, uint32_t key_rows, int32_t *value);
+
 void he_free_layer(he_layer *layer);
 void he_free(he_ctx *ctx);
 const char *he_strerror(int code);

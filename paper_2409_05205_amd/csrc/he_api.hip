@@ -11,9 +11,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+#include <functional>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -123,6 +127,9 @@ struct he_ctx {
     std::unordered_map<hipStream_t, Workspace> ws;
     uint32_t prof_mask = 0;
     std::vector<ProfRec> prof;
+    // tuning: forced knob values (0 / -1 = automatic) and measured choices per launch shape
+    int force_fwd = 0, force_inv = 0, force_tail = 0, force_mac = -1;
+    std::map<std::tuple<int, uint32_t, uint32_t>, int> tuned;   // (knob, log size, rows) -> value
 };
 
 struct he_layer {
@@ -169,6 +176,17 @@ int ctx_workspace(he_ctx *ctx, hipStream_t st, size_t bytes, void **out) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+int knob(he_ctx *ctx, int which, uint32_t logsize, uint32_t rows) {
+    const int forced = which == HE_TUNE_NTT_FWD ? ctx->force_fwd
+                       : which == HE_TUNE_NTT_INV ? ctx->force_inv
+                       : which == HE_TUNE_TAIL ? ctx->force_tail
+                                               : ctx->force_mac;
+    if (which == HE_TUNE_MAC ? forced >= 0 : forced > 0) return forced;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->tuned.find(std::make_tuple(which, logsize, rows));
+    return it == ctx->tuned.end() ? (which == HE_TUNE_MAC ? -1 : 0) : it->second;
+}
+
 // Times one kernel launch with dispatch-recorded events when profiling is on for its kind.
 struct ProfScope {
     he_ctx *ctx;
@@ -190,6 +208,33 @@ struct ProfScope {
         return e;
     }
 };
+
+}  // namespace
+
+namespace {
+
+// Average duration (ms) of `reps` launches made by fn(stream), after two warm-up launches.
+template <class F>
+int time_launches(hipStream_t st, int reps, F fn, double *ms_out) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HE_EDEVICE;
+    int rc = HE_OK;
+    for (int i = 0; i < 2 && rc == HE_OK; ++i)
+        if (fn(st) != hipSuccess) rc = HE_EDEVICE;
+    if (rc == HE_OK) {
+        hipEventRecord(a, st);
+        for (int i = 0; i < reps && rc == HE_OK; ++i)
+            if (fn(st) != hipSuccess) rc = HE_EDEVICE;
+        hipEventRecord(b, st);
+        hipEventSynchronize(b);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, a, b);
+        *ms_out = ms / reps;
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return rc;
+}
 
 }  // namespace
 
@@ -312,6 +357,136 @@ int he_ctx_params(const he_ctx *ctx, uint32_t *N, uint32_t *L, uint32_t *t, uint
         if (primes) primes[l] = ctx->primes[l];
         if (delta_l) delta_l[l] = ctx->delta_l[l];
     }
+    return HE_OK;
+}
+
+int he_tune_force(he_ctx *ctx, uint32_t which, int32_t value) {
+    if (!ctx) return HE_EINVAL;
+    switch (which) {
+        case HE_TUNE_NTT_FWD: ctx->force_fwd = value; break;
+        case HE_TUNE_NTT_INV: ctx->force_inv = value; break;
+        case HE_TUNE_TAIL: ctx->force_tail = value; break;
+        case HE_TUNE_MAC: ctx->force_mac = value; break;
+        default: return HE_EINVAL;
+    }
+    return HE_OK;
+}
+
+
+int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || B == 0) return HE_EINVAL;
+    const he_layer_info &in = ly->info;
+    hipStream_t st = (hipStream_t)stream;
+    const int logN = (int)ctx->logN;
+    const uint32_t N = in.N, L = in.L, Jtot = 2 * in.K_in, c_o = ly->n_rows;
+    void *ws = nullptr;
+    const size_t need = layer_ws_bytes(ly, B);
+    int rc = ctx_workspace(ctx, st, need, &ws);
+    if (rc != HE_OK) return rc;
+    uint32_t *xn = (uint32_t *)ws;
+    uint32_t *mac = (uint32_t *)((char *)ws + align256((size_t)B * Jtot * L * N * 4));
+    const size_t out_words = in.kind == HE_LAYER_CONV ? (size_t)B * in.K_out * L * N : (size_t)B * in.blocks * L * in.n_o_p;
+    uint32_t *out = nullptr;
+    if (hipMalloc((void **)&out, out_words * 4) != hipSuccess) return HE_ENOMEM;
+    // the workspace holds arbitrary words: timing does not depend on the values and no
+    // kernel's addressing does either
+    auto pick = [&](int which, uint32_t key_size, uint32_t key_rows, const std::vector<int> &cands,
+                    const std::function<hipError_t(hipStream_t, int)> &run) -> int {
+        double best = 1e30;
+        int arg = cands.empty() ? 0 : cands[0];
+        for (int c : cands) {
+            double ms = 0;
+            int r = time_launches(st, 5, [&](hipStream_t s) { return run(s, c); }, &ms);
+            if (r != HE_OK) continue;   // an invalid variant for this shape
+            if (ms < best) {
+                best = ms;
+                arg = c;
+            }
+        }
+        hipGetLastError();
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->tuned[std::make_tuple(which, key_size, key_rows)] = arg;
+        return arg;
+    };
+    const std::vector<int> radix{2, 3, 4, 5};
+    const uint32_t rows0 = B * in.K_in * L;
+    for (uint32_t mult : {1u, 2u}) {   // c0 alone (first layer) or c0 + sh
+        FwdJobs jobs;
+        RowMap m;
+        m.J = 1;
+        m.L = L;
+        m.src_b = m.dst_b = (uint64_t)L * N;
+        m.src_j = m.dst_j = 0;
+        m.src_l = m.dst_l = N;
+        jobs.map[0] = jobs.map[1] = m;
+        jobs.src[0] = jobs.src[1] = xn;
+        jobs.dst[0] = jobs.dst[1] = xn;
+        jobs.rows0 = rows0 * mult;
+        pick(HE_TUNE_NTT_FWD, (uint32_t)logN, rows0 * mult, radix, [&](hipStream_t s, int lr) {
+            return launch_ntt_fwd2(logN, lr, jobs, rows0 * mult, ctx->tw, ctx->twsh, ctx->lc, s, nullptr);
+        });
+    }
+    if (in.kind == HE_LAYER_CONV) {
+        const bool cls = in.flags == HE_PACK_CLASS_INTT;
+        if (B >= 2 && (!cls || (in.s >= 2 && in.s <= 128)))
+            pick(HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B, {0, 1}, [&](hipStream_t s, int v) {
+                if (v == 1) return launch_mac_tiled(xn, ly->op, mac, B, Jtot, Jtot, c_o, L, N, in.s, cls, ctx->lc, s);
+                return cls ? launch_mac_class(xn, ly->op, mac, B, Jtot, Jtot, c_o, L, N, in.s, ctx->lc, s)
+                           : launch_mac_full(xn, ly->op, mac, B, Jtot, Jtot, c_o, L, N, ctx->lc, s);
+            });
+        if (cls) {
+            const uint32_t logm = (uint32_t)logN - log2u(in.s);
+            if (logm >= 4)
+                pick(HE_TUNE_TAIL, logm, B * in.K_out * in.g_o * L, radix, [&](hipStream_t s, int lr) {
+                    return launch_tail_rows(mac, out, nullptr, B, c_o, in.g_o, in.K_out, L, N, in.s, ctx->twi,
+                                            ctx->twish, ctx->lc, s, nullptr, lr);
+                });
+        } else {
+            EpiParams ep;
+            std::memset(&ep, 0, sizeof(ep));
+            ep.c_o = c_o;
+            ep.g_o = in.g_o;
+            ep.K_out = in.K_out;
+            ep.s_log = log2u(in.s);
+            ep.out = out;
+            RowMap mi;
+            std::memset(&mi, 0, sizeof(mi));
+            mi.J = 1;
+            mi.L = L;
+            const uint32_t rows = B * in.K_out * in.g_o * L;
+            pick(HE_TUNE_NTT_INV, (uint32_t)logN, rows, radix, [&](hipStream_t s, int lr) {
+                return launch_ntt_inv(logN, mac, out, mi, rows, ctx->twi, ctx->twish, ctx->lc, EPI_CONV_CLASS, ep, s,
+                                      nullptr, lr);
+            });
+        }
+    } else {
+        EpiParams ep;
+        std::memset(&ep, 0, sizeof(ep));
+        ep.n_o_p = in.n_o_p;
+        ep.blocks = in.blocks;
+        ep.out = out;
+        ep.bias = ly->bias;
+        RowMap mi;
+        std::memset(&mi, 0, sizeof(mi));
+        mi.J = 1;
+        mi.L = L;
+        const uint32_t rows = B * in.blocks * L;
+        pick(HE_TUNE_NTT_INV, (uint32_t)logN, rows, radix, [&](hipStream_t s, int lr) {
+            return launch_ntt_inv(logN, mac, out, mi, rows, ctx->twi, ctx->twish, ctx->lc, EPI_FC_PREFIX, ep, s,
+                                  nullptr, lr);
+        });
+    }
+    hipStreamSynchronize(st);
+    hipFree(out);
+    return HE_OK;
+}
+
+int he_tune_get(he_ctx *ctx, uint32_t which, uint32_t key_size, uint32_t key_rows, int32_t *value) {
+    if (!ctx || !value) return HE_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->tuned.find(std::make_tuple((int)which, key_size, key_rows));
+    if (it == ctx->tuned.end()) return HE_EINVAL;
+    *value = it->second;
     return HE_OK;
 }
 
@@ -533,11 +708,16 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
     if (!aligned16(d_c0) || !aligned16(d_out) || !aligned16(d_ws)) return HE_EINVAL;
     if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
     const he_layer_info &in = ly->info;
-    const uint32_t N = in.N, L = in.L, K_in = in.K_in, Jtot = 2 * K_in;
+    const uint32_t N = in.N, L = in.L, K_in = in.K_in, Jtot = 2 * K_in, c_o = ly->n_rows;
+    const int logN = (int)ctx->logN;
     hipStream_t st = (hipStream_t)stream;
     uint32_t *xn = (uint32_t *)d_ws;
     uint32_t *mac = (uint32_t *)((char *)d_ws + align256((size_t)B * Jtot * L * N * 4));
-    RowMap m;
+    hipError_t e;
+
+    // a1: forward NTT of c0 (rows b, j, l) and, in the same launch, of sh (same coefficients every limb)
+    FwdJobs jobs;
+    RowMap &m = jobs.map[0];
     m.J = K_in;
     m.L = L;
     m.src_b = (uint64_t)K_in * L * N;
@@ -546,46 +726,53 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
     m.dst_b = (uint64_t)Jtot * L * N;
     m.dst_j = (uint64_t)L * N;
     m.dst_l = N;
-    hipError_t e;
-    ProfScope ps1(ctx, HE_K_NTT_FWD);
-        if ((e = ps1.done(launch_ntt_fwd((int)ctx->logN, d_c0, xn, m, B * K_in * L, ctx->tw, ctx->twsh, ctx->lc, st, ps1.ev()))) != hipSuccess)
-        return dev_fail(e, "conv ntt c0");
-    if (d_sh) {
-        RowMap ms = m;
-        ms.src_b = (uint64_t)K_in * N;
-        ms.src_j = N;
-        ms.src_l = 0;
-        ProfScope ps2(ctx, HE_K_NTT_FWD);
-        if ((e = ps2.done(launch_ntt_fwd((int)ctx->logN, d_sh, xn + (size_t)K_in * L * N, ms,
-                                B * K_in * L, ctx->tw, ctx->twsh, ctx->lc, st, ps2.ev()))) != hipSuccess)
-            return dev_fail(e, "conv ntt sh");
+    jobs.src[0] = d_c0;
+    jobs.dst[0] = xn;
+    jobs.rows0 = B * K_in * L;
+    jobs.map[1] = m;
+    jobs.map[1].src_b = (uint64_t)K_in * N;
+    jobs.map[1].src_j = N;
+    jobs.map[1].src_l = 0;
+    jobs.src[1] = d_sh ? d_sh : d_c0;
+    jobs.dst[1] = xn + (size_t)K_in * L * N;
+    const uint32_t fwd_rows = jobs.rows0 * (d_sh ? 2 : 1);
+    {
+        ProfScope ps(ctx, HE_K_NTT_FWD);
+        e = launch_ntt_fwd2(logN, knob(ctx, HE_TUNE_NTT_FWD, (uint32_t)logN, fwd_rows), jobs, fwd_rows, ctx->tw,
+                            ctx->twsh, ctx->lc, st, ps.ev());
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "conv forward ntt");
     }
+    // a2: coefficient-wise MAC over the input rows
     const uint32_t Juse = d_sh ? Jtot : K_in;
-    if (in.flags == HE_PACK_CLASS_INTT) {
-        ProfScope ps3(ctx, HE_K_MAC);
-        e = (B >= 4 && in.s >= 2 && in.s <= 128)
-                ? launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, true, ctx->lc, st, ps3.ev())
-                : launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, ctx->lc, st, ps3.ev());
-        if ((e = ps3.done(e)) != hipSuccess)
-            return dev_fail(e, "conv mac");
-        ProfScope ps4(ctx, HE_K_TAIL);
-        const bool rows_form = (ctx->logN - log2u(in.s)) >= 4;
-        e = rows_form ? launch_tail_rows(mac, d_out, d_sh_next, B, ly->n_rows, in.g_o, in.K_out, L, N, in.s, ctx->twi,
-                                         ctx->twish, ctx->lc, st, ps4.ev())
-                      : launch_tail_class(mac, d_out, d_sh_next, B, ly->n_rows, in.g_o, in.K_out, L, N, in.s,
-                                          ctx->twi, ctx->twish, ctx->lc, st, ps4.ev());
-        if ((e = ps4.done(e)) != hipSuccess)
-            return dev_fail(e, "conv tail");
+    const bool cls = in.flags == HE_PACK_CLASS_INTT;
+    {
+        const int mk = knob(ctx, HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B);
+        const bool tiled_ok = B >= 2 && (!cls || (in.s >= 2 && in.s <= 128));
+        const bool tiled = tiled_ok && (mk < 0 ? B >= 4 : mk == 1);
+        ProfScope ps(ctx, HE_K_MAC);
+        if (tiled)
+            e = launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, cls, ctx->lc, st, ps.ev());
+        else if (cls)
+            e = launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, ctx->lc, st, ps.ev());
+        else
+            e = launch_mac_full(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, ctx->lc, st, ps.ev());
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "conv mac");
+    }
+    // a3 + a4: inverse transform, residue-class extraction, + Delta sh'
+    if (cls) {
+        const uint32_t logm = (uint32_t)logN - log2u(in.s);
+        ProfScope ps(ctx, HE_K_TAIL);
+        if (logm >= 4)
+            e = launch_tail_rows(mac, d_out, d_sh_next, B, c_o, in.g_o, in.K_out, L, N, in.s, ctx->twi, ctx->twish,
+                                 ctx->lc, st, ps.ev(), knob(ctx, HE_TUNE_TAIL, logm, B * in.K_out * in.g_o * L));
+        else
+            e = launch_tail_class(mac, d_out, d_sh_next, B, c_o, in.g_o, in.K_out, L, N, in.s, ctx->twi, ctx->twish,
+                                  ctx->lc, st, ps.ev());
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "conv tail");
     } else {
-        ProfScope ps5(ctx, HE_K_MAC);
-        e = (B >= 4) ? launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, in.s, false, ctx->lc, st,
-                                        ps5.ev())
-                     : launch_mac_full(xn, ly->op, mac, B, Jtot, Juse, ly->n_rows, L, N, ctx->lc, st, ps5.ev());
-        if ((e = ps5.done(e)) != hipSuccess)
-            return dev_fail(e, "conv mac");
         EpiParams ep;
         std::memset(&ep, 0, sizeof(ep));
-        ep.c_o = ly->n_rows;
+        ep.c_o = c_o;
         ep.g_o = in.g_o;
         ep.K_out = in.K_out;
         ep.s_log = log2u(in.s);
@@ -595,10 +782,11 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
         std::memset(&mi, 0, sizeof(mi));
         mi.J = 1;
         mi.L = L;
-        ProfScope ps6(ctx, HE_K_INTT);
-        if ((e = ps6.done(launch_ntt_inv((int)ctx->logN, mac, d_out, mi,
-                 B * in.K_out * in.g_o * L, ctx->twi, ctx->twish, ctx->lc, EPI_CONV_CLASS, ep, st, ps6.ev()))) != hipSuccess)
-            return dev_fail(e, "conv intt");
+        const uint32_t rows = B * in.K_out * in.g_o * L;
+        ProfScope ps(ctx, HE_K_INTT);
+        e = launch_ntt_inv(logN, mac, d_out, mi, rows, ctx->twi, ctx->twish, ctx->lc, EPI_CONV_CLASS, ep, st, ps.ev(),
+                           knob(ctx, HE_TUNE_NTT_INV, (uint32_t)logN, rows));
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "conv inverse ntt");
     }
     return HE_OK;
 }
@@ -623,10 +811,13 @@ int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *
     if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
     const he_layer_info &in = ly->info;
     const uint32_t N = in.N, L = in.L;
+    const int logN = (int)ctx->logN;
     hipStream_t st = (hipStream_t)stream;
     uint32_t *xn = (uint32_t *)d_ws;
     uint32_t *mac = (uint32_t *)((char *)d_ws + align256((size_t)B * 2 * L * N * 4));
-    RowMap m;
+    hipError_t e;
+    FwdJobs jobs;
+    RowMap &m = jobs.map[0];
     m.J = 1;
     m.L = L;
     m.src_b = (uint64_t)L * N;
@@ -635,22 +826,26 @@ int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *
     m.dst_b = (uint64_t)2 * L * N;
     m.dst_j = 0;
     m.dst_l = N;
-    hipError_t e;
-    ProfScope ps7(ctx, HE_K_NTT_FWD);
-        if ((e = ps7.done(launch_ntt_fwd((int)ctx->logN, d_c0, xn, m, B * L, ctx->tw, ctx->twsh, ctx->lc, st, ps7.ev()))) != hipSuccess)
-        return dev_fail(e, "fc ntt c0");
-    if (d_sh) {
-        RowMap ms = m;
-        ms.src_b = N;
-        ms.src_l = 0;
-        ProfScope ps8(ctx, HE_K_NTT_FWD);
-        if ((e = ps8.done(launch_ntt_fwd((int)ctx->logN, d_sh, xn + (size_t)L * N, ms,
-                 B * L, ctx->tw, ctx->twsh, ctx->lc, st, ps8.ev()))) != hipSuccess)
-            return dev_fail(e, "fc ntt sh");
+    jobs.src[0] = d_c0;
+    jobs.dst[0] = xn;
+    jobs.rows0 = B * L;
+    jobs.map[1] = m;
+    jobs.map[1].src_b = N;
+    jobs.map[1].src_l = 0;
+    jobs.src[1] = d_sh ? d_sh : d_c0;
+    jobs.dst[1] = xn + (size_t)L * N;
+    const uint32_t fwd_rows = jobs.rows0 * (d_sh ? 2 : 1);
+    {
+        ProfScope ps(ctx, HE_K_NTT_FWD);
+        e = launch_ntt_fwd2(logN, knob(ctx, HE_TUNE_NTT_FWD, (uint32_t)logN, fwd_rows), jobs, fwd_rows, ctx->tw,
+                            ctx->twsh, ctx->lc, st, ps.ev());
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "fc forward ntt");
     }
-    ProfScope ps9(ctx, HE_K_MAC);
-        if ((e = ps9.done(launch_mac_full(xn, ly->op, mac, B, 2, d_sh ? 2 : 1, in.blocks, L, N, ctx->lc, st, ps9.ev()))) != hipSuccess)
-        return dev_fail(e, "fc mac");
+    {
+        ProfScope ps(ctx, HE_K_MAC);
+        e = launch_mac_full(xn, ly->op, mac, B, 2, d_sh ? 2 : 1, in.blocks, L, N, ctx->lc, st, ps.ev());
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "fc mac");
+    }
     EpiParams ep;
     std::memset(&ep, 0, sizeof(ep));
     ep.n_o_p = in.n_o_p;
@@ -662,10 +857,13 @@ int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *
     std::memset(&mi, 0, sizeof(mi));
     mi.J = 1;
     mi.L = L;
-    ProfScope ps10(ctx, HE_K_INTT);
-        if ((e = ps10.done(launch_ntt_inv((int)ctx->logN, mac, d_out, mi, B * in.blocks * L,
-             ctx->twi, ctx->twish, ctx->lc, EPI_FC_PREFIX, ep, st, ps10.ev()))) != hipSuccess)
-        return dev_fail(e, "fc intt");
+    const uint32_t rows = B * in.blocks * L;
+    {
+        ProfScope ps(ctx, HE_K_INTT);
+        e = launch_ntt_inv(logN, mac, d_out, mi, rows, ctx->twi, ctx->twish, ctx->lc, EPI_FC_PREFIX, ep, st, ps.ev(),
+                           knob(ctx, HE_TUNE_NTT_INV, (uint32_t)logN, rows));
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "fc inverse ntt");
+    }
     return HE_OK;
 }
 

@@ -29,6 +29,14 @@ struct RowMap {
     uint64_t dst_b, dst_j, dst_l;
 };
 
+// One or two forward-transform jobs in a single launch (rows of job 0 first).
+struct FwdJobs {
+    const uint32_t *src[2];
+    uint32_t *dst[2];
+    RowMap map[2];
+    uint32_t rows0;
+};
+
 // Epilogues of the inverse transform.
 enum EpiKind {
     EPI_STORE = 0,        // dst row = result (optionally times N^-1)
@@ -48,15 +56,19 @@ struct EpiParams {
 };
 
 // Forward negacyclic NTT (natural order in, bit-reversed order out), rows of N words.
+// logr = register radix log2 (2..5, threads per row N / 2^logr <= 1024); 0 = default choice.
 hipError_t launch_ntt_fwd(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
-                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
+                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st,
+                          const LaunchEv *ev = nullptr, int logr = 0);
+hipError_t launch_ntt_fwd2(int logn, int logr, const FwdJobs &jobs, uint32_t rows, const uint32_t *tw,
+                           const uint32_t *twsh, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Inverse (bit-reversed in, natural out, unscaled unless EPI_STORE with scale).
 // For EPI_CONV_CLASS rows are (b, g, n', l) with l fastest; src is [B][c_o][L][N].
 // For EPI_FC_PREFIX rows are (b, blk, l); src is [B][blocks][L][N].
 hipError_t launch_ntt_inv(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
                           const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
-                          int epi, const EpiParams &ep, hipStream_t st, const LaunchEv *ev = nullptr);
+                          int epi, const EpiParams &ep, hipStream_t st, const LaunchEv *ev = nullptr, int logr = 0);
 
 // Pointwise MAC, full length: out[b][n][l][k] = sum_{J<Juse} X[b][J][l][k] * Op[n][l][J][k].
 hipError_t launch_mac_full(const uint32_t *X, const uint32_t *Op, uint32_t *out, uint32_t B, uint32_t Jtot,
@@ -86,7 +98,7 @@ hipError_t launch_tail_class(const uint32_t *h, uint32_t *out, const uint32_t *s
 hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
                             uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
-                            const LaunchEv *ev = nullptr);
+                            const LaunchEv *ev = nullptr, int logr = 0);
 
 // Pack-time helpers.
 // Op[n][l][j][k]         = rho[j][n][k]                         for j < K_in

@@ -85,19 +85,21 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], uint32_t *lds
 
 template <int LOGN, int LOGR>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
-k_ntt_fwd(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, RowMap map,
-          const uint32_t *__restrict__ tw, const uint32_t *__restrict__ twsh, LimbConsts lc) {
+k_ntt_fwd(FwdJobs jobs, const uint32_t *__restrict__ tw, const uint32_t *__restrict__ twsh, LimbConsts lc) {
     constexpr int N = 1 << LOGN;
     constexpr int T = 1 << (LOGN - LOGR);
     __shared__ uint32_t lds[N + (N >> 5)];
     const uint32_t tid = threadIdx.x;
-    const uint32_t r = blockIdx.x;
+    uint32_t r = blockIdx.x;
+    const int js = r < jobs.rows0 ? 0 : 1;       // rows of job 0 first, then job 1
+    if (js) r -= jobs.rows0;
+    const RowMap &map = jobs.map[js];
     const uint32_t l = r % map.L;
     const uint32_t jb = r / map.L;
     const uint32_t j = jb % map.J;
     const uint32_t b = jb / map.J;
-    const uint32_t *in = src + b * map.src_b + j * map.src_j + l * map.src_l;
-    uint32_t *out = dst + b * map.dst_b + j * map.dst_j + l * map.dst_l;
+    const uint32_t *in = jobs.src[js] + b * map.src_b + j * map.src_j + l * map.src_l;
+    uint32_t *out = jobs.dst[js] + b * map.dst_b + j * map.dst_j + l * map.dst_l;
     const uint32_t q = lc.l[l].q, q2 = lc.l[l].q2;
     uint32_t v[1 << LOGR];
     fwd_pass<LOGN, LOGR, 0>(v, lds, tid, in, tw + (size_t)l * N, twsh + (size_t)l * N, q, q2);
@@ -284,36 +286,47 @@ k_ntt_inv(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, RowMap m
     }
 }
 
-template <int LOGN>
-struct NttCfg {
-    static constexpr int LOGR = (LOGN <= 12) ? 4 : 5;
-    static constexpr int T = 1 << (LOGN - LOGR);
-};
+// Threads per row T = N / 2^LOGR; a variant is valid when 1 <= T <= 1024.
+constexpr bool valid_variant(int logn, int logr) { return logr >= 2 && logr <= 5 && logr <= logn && logn - logr <= 10; }
 
-template <int LOGN>
-hipError_t fwd_dispatch(const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
-                        const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st,
-                        const LaunchEv *ev) {
-    using C = NttCfg<LOGN>;
-    HE_LAUNCH(ev, (k_ntt_fwd<LOGN, C::LOGR>), dim3(rows), dim3(C::T), 0, st, src, dst, map, tw, twsh, lc);
-    return hipGetLastError();
+// Default register radix: enough rows to fill the chip -> 2^5 words per thread
+// (fewer, longer threads); a handful of rows -> more threads per row.
+inline int default_logr(int logn, uint32_t rows) {
+    if (rows >= 128) return logn <= 12 ? 4 : 5;
+    const int lr = logn - 10 > 3 ? logn - 10 : 3;   // up to 1024 threads per row
+    return lr < logn ? lr : logn;
 }
 
-template <int LOGN>
-hipError_t inv_dispatch(const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
-                        const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc, int epi,
-                        const EpiParams &ep, hipStream_t st, const LaunchEv *ev) {
-    using C = NttCfg<LOGN>;
-    if (epi == EPI_STORE)
-        HE_LAUNCH(ev, (k_ntt_inv<LOGN, C::LOGR, EPI_STORE>), dim3(rows), dim3(C::T), 0, st, src, dst, map, twi,
-                  twish, lc, ep);
-    else if (epi == EPI_CONV_CLASS)
-        HE_LAUNCH(ev, (k_ntt_inv<LOGN, C::LOGR, EPI_CONV_CLASS>), dim3(rows), dim3(C::T), 0, st, src, dst, map,
-                  twi, twish, lc, ep);
-    else
-        HE_LAUNCH(ev, (k_ntt_inv<LOGN, C::LOGR, EPI_FC_PREFIX>), dim3(rows), dim3(C::T), 0, st, src, dst, map,
-                  twi, twish, lc, ep);
-    return hipGetLastError();
+template <int LOGN, int LOGR>
+hipError_t fwd_launch(const FwdJobs &jobs, uint32_t rows, const uint32_t *tw, const uint32_t *twsh,
+                      const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
+    if constexpr (valid_variant(LOGN, LOGR)) {
+        HE_LAUNCH(ev, (k_ntt_fwd<LOGN, LOGR>), dim3(rows), dim3(1 << (LOGN - LOGR)), 0, st, jobs, tw, twsh, lc);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int LOGN, int LOGR>
+hipError_t inv_launch(const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows, const uint32_t *twi,
+                      const uint32_t *twish, const LimbConsts &lc, int epi, const EpiParams &ep, hipStream_t st,
+                      const LaunchEv *ev) {
+    if constexpr (valid_variant(LOGN, LOGR)) {
+        constexpr int T = 1 << (LOGN - LOGR);
+        if (epi == EPI_STORE)
+            HE_LAUNCH(ev, (k_ntt_inv<LOGN, LOGR, EPI_STORE>), dim3(rows), dim3(T), 0, st, src, dst, map, twi, twish,
+                      lc, ep);
+        else if (epi == EPI_CONV_CLASS)
+            HE_LAUNCH(ev, (k_ntt_inv<LOGN, LOGR, EPI_CONV_CLASS>), dim3(rows), dim3(T), 0, st, src, dst, map, twi,
+                      twish, lc, ep);
+        else
+            HE_LAUNCH(ev, (k_ntt_inv<LOGN, LOGR, EPI_FC_PREFIX>), dim3(rows), dim3(T), 0, st, src, dst, map, twi,
+                      twish, lc, ep);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 // ------------------------------------------------------------------ residue-class tail
@@ -324,7 +337,7 @@ hipError_t inv_dispatch(const uint32_t *src, uint32_t *dst, const RowMap &map, u
 // inverse table), then writes the span of residue classes its channels own:
 // out_g[s m + c] for c in [c_lo, c_lo + RW s / g_o), every m < M.
 template <int LOGM, int LOGR>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const uint32_t *__restrict__ sh_next,
             uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, uint32_t RW,
             const uint32_t *__restrict__ twi, const uint32_t *__restrict__ twish, LimbConsts lc) {
@@ -386,70 +399,113 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
     }
 }
 
-template <int LOGM>
-hipError_t tail_dispatch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
-                         uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log,
-                         const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
-                         const LaunchEv *ev) {
-    constexpr int LOGR = (LOGM <= 12) ? 4 : 5;
-    constexpr int T = 1 << (LOGM - LOGR);
-    constexpr int TPW = T < 256 ? 256 : T;
-    uint32_t RW = TPW / T;
-    if (RW > g_o) RW = g_o;
-    const uint32_t grid = B * K_out * L * (g_o / RW);
-    const size_t lds = (size_t)(TPW / T) * ((1u << LOGM) + (1u << LOGM >> 5)) * sizeof(uint32_t);
-    HE_LAUNCH(ev, (k_tail_rows<LOGM, LOGR>), dim3(grid), dim3(TPW), lds, st, h, out, sh_next, c_o, g_o, K_out, L,
-              logN, s_log, RW, twi, twish, lc);
-    return hipGetLastError();
+template <int LOGM, int LOGR>
+hipError_t tail_launch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
+                       uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, const uint32_t *twi,
+                       const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
+    if constexpr (valid_variant(LOGM, LOGR)) {
+        constexpr int T = 1 << (LOGM - LOGR);
+        constexpr int TPW = T < 256 ? 256 : T;
+        uint32_t RW = TPW / T;
+        if (RW > g_o) RW = g_o;
+        const uint32_t grid = B * K_out * L * (g_o / RW);
+        const size_t lds = (size_t)(TPW / T) * ((1u << LOGM) + (1u << LOGM >> 5)) * sizeof(uint32_t);
+        HE_LAUNCH(ev, (k_tail_rows<LOGM, LOGR>), dim3(grid), dim3(TPW), lds, st, h, out, sh_next, c_o, g_o, K_out,
+                  L, logN, s_log, RW, twi, twish, lc);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_ntt_fwd(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
-                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st,
-                          const LaunchEv *ev) {
+#define HE_SWITCH_LOGR(LN, LR, CALL)          \
+    switch (LR) {                              \
+        case 2: return CALL(LN, 2);            \
+        case 3: return CALL(LN, 3);            \
+        case 4: return CALL(LN, 4);            \
+        case 5: return CALL(LN, 5);            \
+        default: return hipErrorInvalidValue;  \
+    }
+
+hipError_t launch_ntt_fwd2(int logn, int logr, const FwdJobs &jobs, uint32_t rows, const uint32_t *tw,
+                           const uint32_t *twsh, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
     if (rows == 0) return hipSuccess;
+    if (logr == 0 || !valid_variant(logn, logr)) logr = default_logr(logn, rows);
+#define HE_FWD(LN, LR) fwd_launch<LN, LR>(jobs, rows, tw, twsh, lc, st, ev)
     switch (logn) {
-        case 8: return fwd_dispatch<8>(src, dst, map, rows, tw, twsh, lc, st, ev);
-        case 9: return fwd_dispatch<9>(src, dst, map, rows, tw, twsh, lc, st, ev);
-        case 10: return fwd_dispatch<10>(src, dst, map, rows, tw, twsh, lc, st, ev);
-        case 11: return fwd_dispatch<11>(src, dst, map, rows, tw, twsh, lc, st, ev);
-        case 12: return fwd_dispatch<12>(src, dst, map, rows, tw, twsh, lc, st, ev);
-        case 13: return fwd_dispatch<13>(src, dst, map, rows, tw, twsh, lc, st, ev);
-        case 14: return fwd_dispatch<14>(src, dst, map, rows, tw, twsh, lc, st, ev);
+        case 8: HE_SWITCH_LOGR(8, logr, HE_FWD)
+        case 9: HE_SWITCH_LOGR(9, logr, HE_FWD)
+        case 10: HE_SWITCH_LOGR(10, logr, HE_FWD)
+        case 11: HE_SWITCH_LOGR(11, logr, HE_FWD)
+        case 12: HE_SWITCH_LOGR(12, logr, HE_FWD)
+        case 13: HE_SWITCH_LOGR(13, logr, HE_FWD)
+        case 14: HE_SWITCH_LOGR(14, logr, HE_FWD)
         default: return hipErrorInvalidValue;
     }
+#undef HE_FWD
+}
+
+hipError_t launch_ntt_fwd(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
+                          const uint32_t *tw, const uint32_t *twsh, const LimbConsts &lc, hipStream_t st,
+                          const LaunchEv *ev, int logr) {
+    FwdJobs jobs;
+    jobs.src[0] = jobs.src[1] = src;
+    jobs.dst[0] = jobs.dst[1] = dst;
+    jobs.map[0] = jobs.map[1] = map;
+    jobs.rows0 = rows;
+    return launch_ntt_fwd2(logn, logr, jobs, rows, tw, twsh, lc, st, ev);
 }
 
 hipError_t launch_ntt_inv(int logn, const uint32_t *src, uint32_t *dst, const RowMap &map, uint32_t rows,
                           const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc, int epi,
-                          const EpiParams &ep, hipStream_t st, const LaunchEv *ev) {
+                          const EpiParams &ep, hipStream_t st, const LaunchEv *ev, int logr) {
     if (rows == 0) return hipSuccess;
+    if (logr == 0 || !valid_variant(logn, logr)) logr = default_logr(logn, rows);
+#define HE_INV(LN, LR) inv_launch<LN, LR>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev)
     switch (logn) {
-        case 8: return inv_dispatch<8>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
-        case 9: return inv_dispatch<9>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
-        case 10: return inv_dispatch<10>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
-        case 11: return inv_dispatch<11>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
-        case 12: return inv_dispatch<12>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
-        case 13: return inv_dispatch<13>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
-        case 14: return inv_dispatch<14>(src, dst, map, rows, twi, twish, lc, epi, ep, st, ev);
+        case 8: HE_SWITCH_LOGR(8, logr, HE_INV)
+        case 9: HE_SWITCH_LOGR(9, logr, HE_INV)
+        case 10: HE_SWITCH_LOGR(10, logr, HE_INV)
+        case 11: HE_SWITCH_LOGR(11, logr, HE_INV)
+        case 12: HE_SWITCH_LOGR(12, logr, HE_INV)
+        case 13: HE_SWITCH_LOGR(13, logr, HE_INV)
+        case 14: HE_SWITCH_LOGR(14, logr, HE_INV)
         default: return hipErrorInvalidValue;
     }
+#undef HE_INV
 }
 
 hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
                             uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
-                            const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
+                            const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev,
+                            int logr) {
     if (B == 0) return hipSuccess;
     uint32_t logN = 0, s_log = 0;
     while ((1u << logN) < N) ++logN;
     while ((1u << s_log) < s) ++s_log;
-    switch (logN - s_log) {
-#define HE_TAIL_CASE(LM) \
-    case LM: return tail_dispatch<LM>(h, out, sh_next, B, c_o, g_o, K_out, L, logN, s_log, twi, twish, lc, st, ev);
-        HE_TAIL_CASE(4) HE_TAIL_CASE(5) HE_TAIL_CASE(6) HE_TAIL_CASE(7) HE_TAIL_CASE(8) HE_TAIL_CASE(9)
-        HE_TAIL_CASE(10) HE_TAIL_CASE(11) HE_TAIL_CASE(12) HE_TAIL_CASE(13) HE_TAIL_CASE(14)
-#undef HE_TAIL_CASE
+    const int logm = (int)(logN - s_log);
+    if (logr != 0 && !valid_variant(logm, logr)) logr = 0;
+    if (logr == 0) {
+        const uint32_t rows = B * K_out * g_o * L;
+        logr = rows >= 1024 ? (logm <= 12 ? 4 : 5) : (logm - 8 > 2 ? logm - 8 : 2);   // few rows: 256 threads/row
+        if (logr > logm) logr = logm;
+    }
+#define HE_TAIL(LM, LR) tail_launch<LM, LR>(h, out, sh_next, B, c_o, g_o, K_out, L, logN, s_log, twi, twish, lc, st, ev)
+    switch (logm) {
+        case 4: HE_SWITCH_LOGR(4, logr, HE_TAIL)
+        case 5: HE_SWITCH_LOGR(5, logr, HE_TAIL)
+        case 6: HE_SWITCH_LOGR(6, logr, HE_TAIL)
+        case 7: HE_SWITCH_LOGR(7, logr, HE_TAIL)
+        case 8: HE_SWITCH_LOGR(8, logr, HE_TAIL)
+        case 9: HE_SWITCH_LOGR(9, logr, HE_TAIL)
+        case 10: HE_SWITCH_LOGR(10, logr, HE_TAIL)
+        case 11: HE_SWITCH_LOGR(11, logr, HE_TAIL)
+        case 12: HE_SWITCH_LOGR(12, logr, HE_TAIL)
+        case 13: HE_SWITCH_LOGR(13, logr, HE_TAIL)
+        case 14: HE_SWITCH_LOGR(14, logr, HE_TAIL)
         default: return hipErrorInvalidValue;
     }
+#undef HE_TAIL
 }

@@ -31,7 +31,9 @@ EXPORTED = [
     "he_seq_free",
     "he_server_create", "he_server_add_layer", "he_server_add_request", "he_server_run", "he_server_requests",
     "he_server_results", "he_server_free",
+    "he_tune_force", "he_autotune_layer", "he_tune_get",
 ]
+HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
 HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT = 1, 2, 4, 8
 
 
@@ -110,6 +112,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     D = P(ctypes.c_double)
     lib.he_server_results.argtypes = [VP, D, D, D, P(U32), P(ctypes.c_int32)]
     lib.he_server_free.argtypes = [VP]
+    lib.he_tune_force.argtypes = [VP, U32, ctypes.c_int32]
+    lib.he_autotune_layer.argtypes = [VP, VP, U32, VP]
+    lib.he_tune_get.argtypes = [VP, U32, U32, U32, P(ctypes.c_int32)]
     lib.he_free_layer.argtypes = [VP]
     lib.he_free.argtypes = [VP]
     lib.he_strerror.argtypes = [ctypes.c_int]
@@ -323,6 +328,18 @@ class Context:
         _check(load_library().he_poly_mul(self.handle, rows, _ptr(a), _ptr(b), _ptr(out), _stream(stream)),
                "he_poly_mul")
         return out
+
+    # ---------------------------------------------------------- tuning
+    def tune_force(self, knob: int, value: int) -> None:
+        _check(load_library().he_tune_force(self.handle, knob, value), "he_tune_force")
+
+    def autotune(self, layer: Layer, B: int, stream=None) -> None:
+        _check(load_library().he_autotune_layer(self.handle, layer.handle, B, _stream(stream)), "he_autotune_layer")
+
+    def tune_get(self, knob: int, key_size: int, key_rows: int) -> Optional[int]:
+        v = ctypes.c_int32()
+        rc = load_library().he_tune_get(self.handle, knob, key_size, key_rows, ctypes.byref(v))
+        return int(v.value) if rc == HE_OK else None
 
     # ---------------------------------------------------------- kernel timing
     def profile_enable(self, kind_mask: int) -> None:
