@@ -190,6 +190,39 @@ int he_profile_read(he_ctx *ctx, uint32_t kind, uint64_t *launches, double *tota
 int he_profile_reset(he_ctx *ctx);
 
 /*
+ * Client role (the client side of Alg. 1 / Alg. 2 on the device).
+ *
+ * he_pack_operands -- a layer whose resident NTT-domain operands are two given
+ * polynomial sets instead of (rho, -Delta fhat): a, b host u32 residues,
+ * conv [K_in][c_o][L][N], fc [blocks][L][N], coefficient form, each below its
+ * limb's prime (HE_EINVAL otherwise).  Calling he_conv_layer / he_fc_layer on
+ * it with d_c0 = a per-limb input set X and d_sh = a [0, t) input set Y gives
+ * sum_j X_j a_j + Y_j b_j with the same extraction.  With a = p1, b = p2
+ * (the masks of the server initialisation) and X = v, Y = i this is the
+ * client's c1^r (Alg. 1 / Alg. 2 client evaluation); pass d_sh_next = NULL.
+ *
+ * he_encrypt_c0 -- c0 of the encryption of -msg (Alg. 1 / Alg. 2 client
+ * encryption, Eq. encryption negated): out[r] = -(v[r] b + Delta msg[r] + e0[r])
+ * mod q_l.  v, e0: device int32 [rows][N] (small signed), b: device [L][N]
+ * residues (public key part), msg: device [rows][N] values < t, out:
+ * [rows][L][N].  With v = s, b = a, msg = 0, e0 = -e it is key generation
+ * b = -a s + e (Sec. II-A).  Uses the context workspace.
+ *
+ * he_decrypt -- msg[r][k] = round(t x / Q) mod t, x the CRT lift of
+ * x0[r][.][k] + x1[r][.][k] (x1 may be NULL): the scale-and-round of the share
+ * sum (Alg. 1 / Alg. 2 last client line, Eq. decryption in the exact reading).
+ * x0, x1: device [rows][L][M] residues; msg: [rows][M]; M <= N (0 means N),
+ * e.g. M = n_o' for FC outputs.  Correct for share sums within Q/(4t) of
+ * Delta times a message.
+ */
+int he_pack_operands(he_ctx *ctx, const he_layer_desc *desc, const uint32_t *a, const uint32_t *b,
+                     uint32_t flags, he_layer **out);
+int he_encrypt_c0(he_ctx *ctx, uint32_t rows, const int32_t *d_v, const uint32_t *d_b,
+                  const uint32_t *d_msg, const int32_t *d_e0, uint32_t *d_out, void *stream);
+int he_decrypt(he_ctx *ctx, uint32_t rows, uint32_t M, const uint32_t *d_x0, const uint32_t *d_x1,
+               uint32_t *d_msg, void *stream);
+
+/*
  * Layer sequences (runtime): an ordered list of layer calls with their device
  * buffers, run as one host call or captured once into a HIP graph and replayed.
  * Steps run in order on one stream and share one sequence-owned workspace, so a
@@ -239,6 +272,13 @@ int he_server_create(const he_server_config *cfg, he_server **out);
 int he_server_add_layer(he_server *srv, he_ctx *ctx, const he_layer *layer, uint32_t *layer_id);
 int he_server_add_request(he_server *srv, uint32_t layer_id, double arrival_s, const uint32_t *d_c0,
                           const uint32_t *d_sh, const uint32_t *d_sh_next, uint32_t *d_out);
+/* As he_server_add_request, but the request is held until request `after` (an
+ * index of an earlier added request, -1 for none) completes; it then arrives at
+ * max(arrival_s, that completion time).  This models a client that issues its
+ * next layer when the previous one returns.  If `after` fails, so does this. */
+int he_server_add_request_after(he_server *srv, uint32_t layer_id, double arrival_s, int64_t after,
+                                const uint32_t *d_c0, const uint32_t *d_sh, const uint32_t *d_sh_next,
+                                uint32_t *d_out);
 int he_server_run(he_server *srv);
 uint32_t he_server_requests(const he_server *srv);
 int he_server_results(const he_server *srv, double *arrival, double *dispatch, double *complete,

@@ -128,6 +128,7 @@ struct he_ctx {
     uint32_t prof_mask = 0;
     std::vector<ProfRec> prof;
     // tuning: forced knob values (0 / -1 = automatic) and measured choices per launch shape
+    DecConsts dc;
     int force_fwd = 0, force_inv = 0, force_tail = 0, force_mac = -1;
     std::map<std::tuple<int, uint32_t, uint32_t>, int> tuned;   // (knob, log size, rows) -> value
 };
@@ -332,6 +333,16 @@ int he_setup(uint32_t N, uint32_t L, const uint32_t *primes, uint32_t t, he_ctx 
         c.ninv_sh = shoup(c.ninv, q);
         c.t_mod = t;
         ctx->delta_l.push_back(c.delta);
+    }
+    // decryption: (Q / q_l)^-1 mod q_l
+    std::memset(&ctx->dc, 0, sizeof(ctx->dc));
+    ctx->dc.t = t;
+    for (uint32_t l = 0; l < L; ++l) {
+        uint64_t prod = 1;
+        for (uint32_t k = 0; k < L; ++k)
+            if (k != l) prod = mulmod(prod, ps[k] % ps[l], ps[l]);
+        ctx->dc.inv[l] = (uint32_t)invmod(prod, ps[l]);
+        ctx->dc.inv_sh[l] = shoup(ctx->dc.inv[l], ps[l]);
     }
     const size_t bytes = (size_t)L * N * 4;
     uint32_t **bufs[5] = {&ctx->tw, &ctx->twsh, &ctx->twi, &ctx->twish, &ctx->xinv};
@@ -698,6 +709,177 @@ int he_pack_filters(he_ctx *ctx, const he_layer_desc *desc, const int8_t *weight
     hipFree(d_cls);
     *out = ly;
     return HE_OK;
+}
+
+namespace {
+
+// Tiling of a layer description (the rule in include/he.h); cls gets o_n per channel (conv).
+int layer_geometry(const he_ctx *ctx, const he_layer_desc *desc, uint32_t flags, he_layer_info *info,
+                   std::vector<uint32_t> *cls) {
+    const uint32_t N = ctx->N;
+    std::memset(info, 0, sizeof(*info));
+    info->kind = desc->kind;
+    info->N = N;
+    info->L = ctx->L;
+    if (desc->kind == HE_LAYER_CONV) {
+        const uint32_t c_i = desc->c_i, c_o = desc->c_o, H = desc->H, W = desc->W, f = desc->f;
+        if (!c_i || !c_o || !H || !W || !f || !desc->stride) return HE_EINVAL;
+        const uint64_t Hp = (uint64_t)H + 2 * desc->pad, Wp = (uint64_t)W + 2 * desc->pad;
+        if (f > Hp || f > Wp || Hp * Wp > N) return HE_EINVAL;
+        const uint32_t s = pow2_floor((uint32_t)(N / (Hp * Wp)));
+        if (s > 256) return HE_EUNSUPPORTED;
+        info->s = s;
+        info->g_i = c_i < s ? c_i : s;
+        info->g_o = pow2_floor(c_o < s ? c_o : s);
+        info->K_in = (c_i + info->g_i - 1) / info->g_i;
+        info->K_out = (c_o + info->g_o - 1) / info->g_o;
+        info->H_p = (uint32_t)Hp;
+        info->W_p = (uint32_t)Wp;
+        info->H_o = (uint32_t)((Hp - f) / desc->stride + 1);
+        info->W_o = (uint32_t)((Wp - f) / desc->stride + 1);
+        info->flags = flags;
+        if (cls) {
+            cls->resize(c_o);
+            for (uint32_t n = 0; n < c_o; ++n) (*cls)[n] = (n % info->g_o) * (s / info->g_o);
+        }
+        return HE_OK;
+    }
+    if (desc->kind == HE_LAYER_FC) {
+        const uint32_t n_i = desc->n_i, n_o = desc->n_o;
+        if (!n_i || !n_o || n_i > N) return HE_EINVAL;
+        uint32_t nop = 1;
+        while (nop < n_o) nop <<= 1;
+        if ((uint64_t)n_i * nop > N) nop = pow2_floor(N / n_i);
+        info->n_o_p = nop;
+        info->n_i_p = N / nop;
+        info->blocks = (n_o + nop - 1) / nop;
+        info->K_in = 1;
+        info->flags = HE_PACK_FULL_INTT;
+        return HE_OK;
+    }
+    return HE_EINVAL;
+}
+
+}  // namespace
+
+int he_pack_operands(he_ctx *ctx, const he_layer_desc *desc, const uint32_t *a, const uint32_t *b, uint32_t flags,
+                     he_layer **out) {
+    if (!ctx || !desc || !a || !b || !out) return HE_EINVAL;
+    if (flags != HE_PACK_CLASS_INTT && flags != HE_PACK_FULL_INTT) return HE_EINVAL;
+    he_layer_info info;
+    std::vector<uint32_t> cls;
+    int rc = layer_geometry(ctx, desc, flags, &info, &cls);
+    if (rc != HE_OK) return rc;
+    const uint32_t N = ctx->N, L = ctx->L, K_in = info.K_in, Jtot = 2 * K_in;
+    const uint32_t n_rows = desc->kind == HE_LAYER_CONV ? desc->c_o : info.blocks;
+    // residues must be below their limb's prime
+    const size_t per_op = (size_t)K_in * n_rows * L * N;
+    for (size_t i = 0; i < per_op; ++i) {
+        const uint32_t q = ctx->primes[(i / N) % L];
+        if (a[i] >= q || b[i] >= q) return HE_EINVAL;
+    }
+    he_layer *ly = new (std::nothrow) he_layer();
+    if (!ly) return HE_ENOMEM;
+    ly->ctx = ctx;
+    ly->n_rows = n_rows;
+    const size_t op_words = (size_t)n_rows * L * Jtot * N;
+    std::vector<uint32_t> host(op_words);
+    for (uint32_t n = 0; n < n_rows; ++n)
+        for (uint32_t l = 0; l < L; ++l)
+            for (uint32_t j = 0; j < K_in; ++j) {
+                const size_t src = (((size_t)j * n_rows + n) * L + l) * N;
+                std::memcpy(&host[(((size_t)n * L + l) * Jtot + j) * N], a + src, N * 4);
+                std::memcpy(&host[(((size_t)n * L + l) * Jtot + K_in + j) * N], b + src, N * 4);
+            }
+    std::vector<int32_t> hbias;
+    if (desc->kind == HE_LAYER_FC) hbias.assign((size_t)info.blocks * info.n_o_p, 0);
+    info.resident_bytes = op_words * 4 + hbias.size() * 4;
+    ly->info = info;
+    uint32_t *d_cls = nullptr;
+    hipError_t e;
+    auto fail = [&](hipError_t err, const char *what) {
+        hipFree(d_cls);
+        he_free_layer(ly);
+        return dev_fail(err, what);
+    };
+    if ((e = hipMalloc((void **)&ly->op, op_words * 4)) != hipSuccess) {
+        he_free_layer(ly);
+        return HE_ENOMEM;
+    }
+    if ((e = hipMemcpy(ly->op, host.data(), op_words * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "pack operands copy");
+    if (!hbias.empty()) {
+        if ((e = hipMalloc((void **)&ly->bias, hbias.size() * 4)) != hipSuccess) return fail(e, "pack bias");
+        if ((e = hipMemcpy(ly->bias, hbias.data(), hbias.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(e, "pack bias copy");
+    }
+    if (desc->kind == HE_LAYER_CONV && flags == HE_PACK_CLASS_INTT) {
+        if ((e = hipMalloc((void **)&d_cls, cls.size() * 4)) != hipSuccess) return fail(e, "pack cls");
+        if ((e = hipMemcpy(d_cls, cls.data(), cls.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(e, "pack cls copy");
+    }
+    RowMap m;
+    m.J = Jtot;
+    m.L = L;
+    m.src_b = m.dst_b = (uint64_t)L * Jtot * N;
+    m.src_j = m.dst_j = N;
+    m.src_l = m.dst_l = (uint64_t)Jtot * N;
+    if ((e = launch_ntt_fwd((int)ctx->logN, ly->op, ly->op, m, n_rows * Jtot * L, ctx->tw, ctx->twsh, ctx->lc,
+                            nullptr)) != hipSuccess)
+        return fail(e, "operand ntt");
+    if ((e = launch_scale_operands(ly->op, ctx->xinv, d_cls, Jtot, n_rows, L, N, ctx->lc, nullptr)) != hipSuccess)
+        return fail(e, "operand scale");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(e, "pack sync");
+    hipFree(d_cls);
+    *out = ly;
+    return HE_OK;
+}
+
+int he_encrypt_c0(he_ctx *ctx, uint32_t rows, const int32_t *d_v, const uint32_t *d_b, const uint32_t *d_msg,
+                  const int32_t *d_e0, uint32_t *d_out, void *stream) {
+    if (!ctx) return HE_EINVAL;
+    if (rows == 0) return HE_OK;
+    if (!d_v || !d_b || !d_msg || !d_e0 || !d_out) return HE_EINVAL;
+    const uint32_t N = ctx->N, L = ctx->L;
+    hipStream_t st = (hipStream_t)stream;
+    void *ws = nullptr;
+    const size_t vb_bytes = align256((size_t)rows * L * N * 4);
+    int rc = ctx_workspace(ctx, st, vb_bytes + align256((size_t)L * N * 4), &ws);
+    if (rc != HE_OK) return rc;
+    uint32_t *V = (uint32_t *)ws;
+    uint32_t *Bh = (uint32_t *)((char *)ws + vb_bytes);
+    RowMap m;
+    m.J = 1;
+    m.L = L;
+    m.src_b = m.dst_b = (uint64_t)L * N;
+    m.src_j = m.dst_j = 0;
+    m.src_l = m.dst_l = N;
+    EpiParams ep;
+    std::memset(&ep, 0, sizeof(ep));
+    ep.scale = 1;
+    hipError_t e;
+    if ((e = launch_lift_signed(d_v, V, rows, L, N, ctx->lc, st)) != hipSuccess) return dev_fail(e, "encrypt lift");
+    if ((e = launch_ntt_fwd((int)ctx->logN, V, V, m, rows * L, ctx->tw, ctx->twsh, ctx->lc, st)) != hipSuccess)
+        return dev_fail(e, "encrypt ntt v");
+    if ((e = launch_ntt_fwd((int)ctx->logN, d_b, Bh, m, L, ctx->tw, ctx->twsh, ctx->lc, st)) != hipSuccess)
+        return dev_fail(e, "encrypt ntt b");
+    if ((e = launch_mul_bcast(V, Bh, V, rows, L, N, ctx->lc, st)) != hipSuccess) return dev_fail(e, "encrypt mul");
+    if ((e = launch_ntt_inv((int)ctx->logN, V, V, m, rows * L, ctx->twi, ctx->twish, ctx->lc, EPI_STORE, ep, st)) !=
+        hipSuccess)
+        return dev_fail(e, "encrypt intt");
+    if ((e = launch_encrypt_combine(V, d_msg, d_e0, d_out, rows, L, N, ctx->lc, st)) != hipSuccess)
+        return dev_fail(e, "encrypt combine");
+    return HE_OK;
+}
+
+int he_decrypt(he_ctx *ctx, uint32_t rows, uint32_t M, const uint32_t *d_x0, const uint32_t *d_x1, uint32_t *d_msg,
+               void *stream) {
+    if (!ctx || M > ctx->N) return HE_EINVAL;
+    if (rows == 0) return HE_OK;
+    if (!d_x0 || !d_msg) return HE_EINVAL;
+    if (M == 0) M = ctx->N;
+    hipError_t e = launch_decrypt(d_x0, d_x1, d_msg, rows, ctx->L, M, ctx->lc, ctx->dc, (hipStream_t)stream);
+    return e == hipSuccess ? HE_OK : dev_fail(e, "decrypt");
 }
 
 int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,

@@ -100,6 +100,25 @@ hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh
                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
                             const LaunchEv *ev = nullptr, int logr = 0);
 
+// Client-side element-wise kernels (kernels_client.hip).
+struct DecConsts {
+    uint32_t t;
+    uint32_t inv[HE_MAX_LIMBS];      // (Q / q_l)^-1 mod q_l
+    uint32_t inv_sh[HE_MAX_LIMBS];   // Shoup companions
+};
+// out[r][l][k] = a[r][k] mod q_l for signed a
+hipError_t launch_lift_signed(const int32_t *a, uint32_t *out, uint32_t rows, uint32_t L, uint32_t N,
+                              const LimbConsts &lc, hipStream_t st);
+// c[r][l][k] = a[r][l][k] * b[l][k] mod q_l
+hipError_t launch_mul_bcast(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t rows, uint32_t L, uint32_t N,
+                            const LimbConsts &lc, hipStream_t st);
+// out[r][l][k] = -(vb[r][l][k] + Delta_l msg[r][k] + e0[r][k]) mod q_l
+hipError_t launch_encrypt_combine(const uint32_t *vb, const uint32_t *msg, const int32_t *e0, uint32_t *out,
+                                  uint32_t rows, uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st);
+// msg[r][k] = round(t CRT(x0 + x1) / Q) mod t   (x1 may be null)
+hipError_t launch_decrypt(const uint32_t *x0, const uint32_t *x1, uint32_t *msg, uint32_t rows, uint32_t L, uint32_t N,
+                          const LimbConsts &lc, const DecConsts &dc, hipStream_t st);
+
 // Pack-time helpers.
 // Op[n][l][j][k]         = rho[j][n][k]                         for j < K_in
 // Op[n][l][K_in + j][k]  = -Delta_l fhat[j][n][k] mod q_l         (fhat int16)

@@ -46,7 +46,8 @@ struct LayerReg {
 
 struct Req {
     uint32_t layer;
-    double arrival;                    // seconds after start
+    int64_t after = -1;                // request this one waits for (-1: none)
+    double arrival;                    // seconds after start (dependents: when their predecessor completed)
     const uint32_t *c0, *sh, *shn;
     uint32_t *out;
     double dispatch = -1, complete = -1;
@@ -110,6 +111,8 @@ struct he_server {
     int device = 0;
     std::vector<LayerReg> layers;
     std::vector<Req> reqs;
+    std::vector<double> sched;          // scheduled arrival of each request as added
+    std::vector<std::vector<uint32_t>> dependents;
     std::vector<Slot> slots;
     void *pool_base = nullptr;
     Pool pool;
@@ -183,6 +186,7 @@ int launch_batch(he_server *s, Slot &sl, const std::vector<uint32_t> &ids) {
 void generator(he_server *s) {
     hipSetDevice(s->device);
     for (uint32_t i = 0; i < s->reqs.size(); ++i) {
+        if (s->reqs[i].after >= 0) continue;   // released by the dispatcher when its predecessor completes
         const double due = s->reqs[i].arrival;
         while (now_s(s) < due && !s->aborted) {
             const double left = due - now_s(s);
@@ -192,6 +196,23 @@ void generator(he_server *s) {
         s->inbox.push_back(i);
     }
     s->gen_done = true;
+}
+
+// A finished request lets its dependents arrive now; the dependents of a failed
+// request fail with it (recursively).
+void release_dependents(he_server *s, uint32_t id, double t, std::deque<uint32_t> &pending, size_t &done) {
+    for (uint32_t d : s->dependents[id]) {
+        Req &r = s->reqs[d];
+        if (s->reqs[id].status != HE_OK) {
+            r.status = s->reqs[id].status;
+            r.arrival = r.dispatch = r.complete = t;
+            ++done;
+            release_dependents(s, d, t, pending, done);
+        } else {
+            if (r.arrival < t) r.arrival = t;
+            pending.push_back(d);
+        }
+    }
 }
 
 void dispatcher(he_server *s) {
@@ -220,6 +241,7 @@ void dispatcher(he_server *s) {
                     if (q != hipSuccess) s->reqs[id].status = HE_EDEVICE;
                 }
                 if (q != hipSuccess && s->first_error == HE_OK) s->first_error = HE_EDEVICE;
+                for (uint32_t id : sl.reqs) release_dependents(s, id, t, pending, done);
                 done += sl.reqs.size();
                 s->pool.release(sl.off, sl.bytes);
                 sl.busy = false;
@@ -257,6 +279,7 @@ void dispatcher(he_server *s) {
                     s->reqs[head].complete = s->reqs[head].dispatch = now_s(s);
                     pending.pop_front();
                     ++done;
+                    release_dependents(s, head, s->reqs[head].complete, pending, done);
                     if (s->first_error == HE_OK) s->first_error = HE_ENOMEM;
                     progressed = true;
                 }
@@ -282,6 +305,7 @@ void dispatcher(he_server *s) {
                     s->reqs[id].status = rc;
                     s->reqs[id].complete = now_s(s);
                 }
+                for (uint32_t id : ids) release_dependents(s, id, now_s(s), pending, done);
                 if (s->first_error == HE_OK) s->first_error = rc;
                 done += ids.size();
                 s->pool.release(off, need);
@@ -357,27 +381,46 @@ int he_server_add_layer(he_server *s, he_ctx *ctx, const he_layer *ly, uint32_t 
     return HE_OK;
 }
 
-int he_server_add_request(he_server *s, uint32_t layer_id, double arrival_s, const uint32_t *d_c0,
-                          const uint32_t *d_sh, const uint32_t *d_sh_next, uint32_t *d_out) {
+int he_server_add_request_after(he_server *s, uint32_t layer_id, double arrival_s, int64_t after,
+                                const uint32_t *d_c0, const uint32_t *d_sh, const uint32_t *d_sh_next,
+                                uint32_t *d_out) {
     if (!s || layer_id >= s->layers.size() || !d_c0 || !d_out || arrival_s < 0) return HE_EINVAL;
-    if (!s->reqs.empty() && arrival_s < s->reqs.back().arrival) return HE_EINVAL;   // trace is time-ordered
+    if (after >= (int64_t)s->reqs.size() || after < -1) return HE_EINVAL;
+    if (after < 0) {   // independent requests form a time-ordered trace
+        for (size_t i = s->reqs.size(); i-- > 0;)
+            if (s->reqs[i].after < 0) {
+                if (arrival_s < s->sched[i]) return HE_EINVAL;
+                break;
+            }
+    }
     Req r;
     r.layer = layer_id;
+    r.after = after;
     r.arrival = arrival_s;
     r.c0 = d_c0;
     r.sh = d_sh;
     r.shn = d_sh_next;
     r.out = d_out;
     s->reqs.push_back(r);
+    s->sched.push_back(arrival_s);
     return HE_OK;
+}
+
+int he_server_add_request(he_server *s, uint32_t layer_id, double arrival_s, const uint32_t *d_c0,
+                          const uint32_t *d_sh, const uint32_t *d_sh_next, uint32_t *d_out) {
+    return he_server_add_request_after(s, layer_id, arrival_s, -1, d_c0, d_sh, d_sh_next, d_out);
 }
 
 int he_server_run(he_server *s) {
     if (!s) return HE_EINVAL;
-    for (Req &r : s->reqs) {
+    s->dependents.assign(s->reqs.size(), {});
+    for (size_t i = 0; i < s->reqs.size(); ++i) {
+        Req &r = s->reqs[i];
+        r.arrival = s->sched[i];
         r.dispatch = r.complete = -1;
         r.batch = 0;
         r.status = HE_OK;
+        if (r.after >= 0) s->dependents[r.after].push_back((uint32_t)i);
     }
     s->first_error = HE_OK;
     s->aborted = false;

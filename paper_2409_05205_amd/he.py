@@ -32,6 +32,7 @@ EXPORTED = [
     "he_server_create", "he_server_add_layer", "he_server_add_request", "he_server_run", "he_server_requests",
     "he_server_results", "he_server_free",
     "he_tune_force", "he_autotune_layer", "he_tune_get",
+    "he_pack_operands", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
 ]
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
 HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT = 1, 2, 4, 8
@@ -106,12 +107,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_server_create.argtypes = [P(ServerConfig), P(VP)]
     lib.he_server_add_layer.argtypes = [VP, VP, VP, P(U32)]
     lib.he_server_add_request.argtypes = [VP, U32, ctypes.c_double, VP, VP, VP, VP]
+    lib.he_server_add_request_after.argtypes = [VP, U32, ctypes.c_double, ctypes.c_int64, VP, VP, VP, VP]
     lib.he_server_run.argtypes = [VP]
     lib.he_server_requests.argtypes = [VP]
     lib.he_server_requests.restype = U32
     D = P(ctypes.c_double)
     lib.he_server_results.argtypes = [VP, D, D, D, P(U32), P(ctypes.c_int32)]
     lib.he_server_free.argtypes = [VP]
+    lib.he_pack_operands.argtypes = [VP, P(LayerDesc), VP, VP, U32, P(VP)]
+    lib.he_encrypt_c0.argtypes = [VP, U32, VP, VP, VP, VP, VP, VP]
+    lib.he_decrypt.argtypes = [VP, U32, U32, VP, VP, VP, VP]
     lib.he_tune_force.argtypes = [VP, U32, ctypes.c_int32]
     lib.he_autotune_layer.argtypes = [VP, VP, U32, VP]
     lib.he_tune_get.argtypes = [VP, U32, U32, U32, P(ctypes.c_int32)]
@@ -252,6 +257,53 @@ class Context:
                                               None if b is None else b.ctypes.data, 0, ctypes.byref(h)),
                "he_pack_filters")
         return Layer(self, h.value, HE_LAYER_FC)
+
+    def pack_operands(self, spec, a: np.ndarray, b: np.ndarray, flags: int = HE_PACK_CLASS_INTT) -> Layer:
+        """A layer with resident operands NTT(a), NTT(b) (e.g. the client masks p1, p2).
+
+        conv: a, b [K_in][c_o][L][N]; fc: [blocks][L][N]; u32 residues below each limb's prime.
+        """
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.uint32))
+        if a.shape != b.shape:
+            raise ValueError("a and b must have the same shape")
+        if isinstance(spec, FCSpec):
+            d = LayerDesc(HE_LAYER_FC, 0, 0, 0, 0, 0, 0, 0, spec.n_i, spec.n_o)
+            kind = HE_LAYER_FC
+        else:
+            d = LayerDesc(HE_LAYER_CONV, spec.c_i, spec.c_o, spec.H, spec.W, spec.f, spec.stride, spec.pad, 0, 0)
+            kind = HE_LAYER_CONV
+        h = ctypes.c_void_p()
+        _check(load_library().he_pack_operands(self.handle, ctypes.byref(d), a.ctypes.data, b.ctypes.data, flags,
+                                               ctypes.byref(h)), "he_pack_operands")
+        return Layer(self, h.value, kind)
+
+    def encrypt_c0(self, v, b, msg, e0, out=None, stream=None):
+        """out = -(v b + Delta msg + e0) per limb; v, e0 int32 [rows][N], b [L][N], msg [rows][N] < t."""
+        import torch
+        rows = v.shape[0]
+        for name, t, shp in (("v", v, (rows, self.N)), ("b", b, (self.L, self.N)), ("msg", msg, (rows, self.N)),
+                             ("e0", e0, (rows, self.N))):
+            _check_dev(t, shp, name)
+        if out is None:
+            out = torch.empty((rows, self.L, self.N), dtype=torch.int32, device=v.device)
+        _check_dev(out, (rows, self.L, self.N), "out")
+        _check(load_library().he_encrypt_c0(self.handle, rows, _ptr(v), _ptr(b), _ptr(msg), _ptr(e0), _ptr(out),
+                                            _stream(stream)), "he_encrypt_c0")
+        return out
+
+    def decrypt(self, x0, x1=None, out=None, stream=None):
+        """Messages mod t of the share sums x0 + x1: x [rows][L][M] -> [rows][M] (M = N or a prefix length)."""
+        import torch
+        rows, M = x0.shape[0], x0.shape[-1]
+        _check_dev(x0, (rows, self.L, M), "x0")
+        _check_dev(x1, (rows, self.L, M), "x1", True)
+        if out is None:
+            out = torch.empty((rows, M), dtype=torch.int32, device=x0.device)
+        _check_dev(out, (rows, M), "out")
+        _check(load_library().he_decrypt(self.handle, rows, M, _ptr(x0), _ptr(x1), _ptr(out), _stream(stream)),
+               "he_decrypt")
+        return out
 
     def conv_tiling(self, spec) -> dict:
         """The tiling rule of include/he.h (host arithmetic only, for sizing buffers)."""
@@ -451,6 +503,15 @@ class Server:
                 raise ValueError(f"{name} must be a contiguous device tensor")
         _check(load_library().he_server_add_request(self.handle, layer_id, float(arrival_s), _ptr(c0), _ptr(sh),
                                                     _ptr(sh_next), _ptr(out)), "he_server_add_request")
+
+    def add_request_after(self, layer_id: int, arrival_s: float, after: int, c0, sh, sh_next, out) -> None:
+        """A request held until request `after` (index of an earlier request, -1 = none) completes."""
+        for name, t in (("c0", c0), ("out", out)):
+            if t is None or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous device tensor")
+        _check(load_library().he_server_add_request_after(self.handle, layer_id, float(arrival_s), int(after),
+                                                          _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out)),
+               "he_server_add_request_after")
 
     def run(self) -> int:
         """Replay the trace; returns the first error code (0 when every request succeeded)."""

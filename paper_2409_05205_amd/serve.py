@@ -142,3 +142,57 @@ def latency_stats(res, warmup: int):
         "layers_per_s": float(len(lat) / span),
         "mean_batch": float(res["batch"][warmup:].mean()),
     }
+
+
+def run_clients(variant: Variant, buffers: List[LayerBuffers], clients: int, streams: int, max_batch: int,
+                budget: int, start_gap: float = 0.0, timeout_s: float = 0.0):
+    """Every client streams the whole stack: layer k of a client is issued when its layer k-1
+    returns (he_server request dependencies).  Clients start start_gap seconds apart.
+    Returns per-request results plus the request table [client][layer] -> index."""
+    srv = he.Server(streams, max_batch, budget, timeout_s)
+    lids = [srv.add_layer(variant.ctx, ly) for ly in variant.layers]
+    n_layers = len(variant.layers)
+    index = np.zeros((clients, n_layers), dtype=np.int64)
+    idx = 0
+    # independent first layers in arrival order, then the dependent chain of each client
+    for cl in range(clients):
+        b = buffers[0]
+        srv.add_request_after(lids[0], cl * start_gap, -1, b.c0[cl], None if b.sh is None else b.sh[cl],
+                              None if b.shn is None else b.shn[cl], b.out[cl])
+        index[cl, 0] = idx
+        idx += 1
+    for k in range(1, n_layers):
+        b = buffers[k]
+        for cl in range(clients):
+            srv.add_request_after(lids[k], 0.0, int(index[cl, k - 1]), b.c0[cl],
+                                  None if b.sh is None else b.sh[cl], None if b.shn is None else b.shn[cl],
+                                  b.out[cl])
+            index[cl, k] = idx
+            idx += 1
+    rc = srv.run()
+    res = srv.results()
+    srv.free()
+    res["rc"] = rc
+    res["index"] = index
+    return res
+
+
+def client_stats(res):
+    """Per-inference latency (first layer issued to last layer returned) and throughput."""
+    index = res["index"]
+    start = res["arrival"][index[:, 0]]
+    end = res["complete"][index[:, -1]]
+    inf = end - start
+    lat = res["complete"] - res["arrival"]
+    span = res["complete"].max() - res["arrival"].min()
+    return {
+        "clients": int(index.shape[0]),
+        "requests": int(index.size),
+        "failed": int((res["status"] != 0).sum()),
+        "inference_p50_ms": float(np.percentile(inf, 50) * 1e3),
+        "inference_p99_ms": float(np.percentile(inf, 99) * 1e3),
+        "layer_p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "layer_p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "layers_per_s": float(index.size / span),
+        "mean_batch": float(res["batch"].mean()),
+    }

@@ -87,7 +87,7 @@ def test_kernel_timing_counts_launches():
     n_mac, ms = ctx.profile_read(he.HE_K_MAC)
     assert n_mac == 4 and ms > 0
     n_fwd, _ = ctx.profile_read(he.HE_K_NTT_FWD)
-    assert n_fwd == 1 + 2 + 2 + 2       # c0 of every layer, sh of the layers that have one
+    assert n_fwd == 4                   # one launch per layer: c0, and sh when present, together
     n_tail, _ = ctx.profile_read(he.HE_K_TAIL)
     n_intt, _ = ctx.profile_read(he.HE_K_INTT)
     assert n_tail + n_intt == 4
