@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--served-requests", type=int, default=6000)
     ap.add_argument("--served-warmup", type=int, default=500)
     ap.add_argument("--served-rate", type=float, default=2000.0)
+    ap.add_argument("--no-stress", action="store_true")
+    ap.add_argument("--stress-clients", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
@@ -355,6 +357,26 @@ def main():
             log(f"{name}: {json.dumps(sres[name])}")
         result["forms"]["served"] = sres
         del variants, buffers
+        torch.cuda.empty_cache()
+
+    # ---------------- stress: x4 / 100 classes, clients streaming whole inferences
+    if not args.no_stress:
+        from paper_2409_05205_amd import serve
+        C = args.stress_clients
+        log(f"setup: stress x4 (N=16384, 6 limbs, 100 classes), {C} clients")
+        ctx16s = he.Context(16384, 6, wl.T_PLAIN)
+        v4 = serve.pack_variant(4, 100, ctx16s, cfg=wl.CONFIG_STRESS)
+        bufs = serve.client_buffers(v4, C, seed=5)
+        sync()
+        stres = {}
+        for name, streams, mb in [("served", 4, 16), ("plain_fcfs", 1, 1)]:
+            res = serve.run_clients(v4, bufs, C, streams, mb, 24 << 30, timeout_s=300)
+            st = serve.client_stats(res)
+            st.update({"streams": streams, "max_batch": mb, "rc": res["rc"]})
+            stres[name] = st
+            log(f"stress {name}: {json.dumps(st)}")
+        result["forms"]["stress"] = stres
+        del v4, bufs
         torch.cuda.empty_cache()
 
     if not args.no_cpu:
