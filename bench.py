@@ -185,6 +185,8 @@ def main():
     ap.add_argument("--stress-clients", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards across GPUs by "
@@ -207,6 +209,13 @@ def main():
     if not args.no_tune:
         st.autotune()
     sync()
+
+    if args.pmc_calibration:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda:0")     # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        sync()
+        del src, dst
 
     # plain: native runtime, one image, 20 calls back to back
     with torch.cuda.stream(stream):

@@ -45,7 +45,8 @@ def _forward_gpu(imgs, shapes, Ws, Bs):
                           padding=shp.pad)
             y = torch.round(y).long()
         else:
-            y = x @ torch.as_tensor(W, dtype=torch.int64, device="cuda:0").T + torch.as_tensor(B, device="cuda:0")
+            y = torch.round(x.double() @ torch.as_tensor(W, dtype=torch.float64, device="cuda:0").T).long()
+            y = y + torch.as_tensor(B, dtype=torch.int64, device="cuda:0")
         outs.append(y)
         r = torch.clamp(y, min=0)
         mx = r.reshape(r.shape[0], -1).amax(dim=1)
