@@ -34,6 +34,30 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# Shoup Cooley-Tukey butterflies per second of the whole chip (256 CUs, 2.4 GHz): 7.3 per CU-clock,
+# measured at full occupancy for this instruction mix (mul_hi + 2 mul_lo + 6 add/compare).
+BFLY_PEAK_G = 4470.0
+# HBM traffic per launch from the FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a 256 MiB
+# copy), valid while the kernel source is the one that was measured.
+PMC_TRAFFIC = {
+    "mac": {"source": "paper_2409_05205_amd/csrc/kernels_mac.hip",
+            "sha256": "cae9d897f2f731e467e8dcde24cfb8c4ce05881b2e6c7460e371861244928ab9",
+            "bytes_per_launch": 17902686},
+    "ntt_fwd": {"source": "paper_2409_05205_amd/csrc/kernels_ntt.hip",
+                "sha256": "ef74afd2a0e95976aa551fa144b076fe777b22c7d2c24e449af46b7b76089e29",
+                "bytes_per_launch": 1832600},
+}
+
+
+def pmc_traffic(kind):
+    import hashlib
+    rec = PMC_TRAFFIC.get(kind)
+    if rec is None:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
+            return None
+    return rec["bytes_per_launch"]
 
 
 def log(*a):
@@ -113,6 +137,15 @@ class Stack:
             J = i.K_in * (2 if sh is not None else 1)
             out_per = N // i.s if ly.kind == 0 else N
             tot += J * c_o * L * N * 4 + B * J * L * N * 4 + B * c_o * L * out_per * 4
+        return tot
+
+    def butterflies_fwd(self):
+        """Forward-NTT butterflies of one pass (c0 rows, plus sh rows where present)."""
+        L, N = self.ctx.L, self.ctx.N
+        per_row = (N // 2) * (N.bit_length() - 1)
+        tot = 0
+        for ly, B, c0, sh, shn in self.steps:
+            tot += B * ly.info.K_in * L * (2 if sh is not None else 1) * per_row
         return tot
 
     def modmuls(self):
@@ -266,6 +299,21 @@ def main():
     mac_launches_per_step = n_layers
     mac_avg_s = kern["mac"]["total_ms"] / 1e3 / kern["mac"]["launches"]
     achieved = mac_bytes / mac_launches_per_step / mac_avg_s / 1e9
+    roof_mac = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("mac"),
+                "algorithmic_bytes_per_launch": mac_bytes // mac_launches_per_step,
+                "kernel": "k_mac_class / k_mac_full (coefficient-wise MAC)",
+                "launches_per_step": mac_launches_per_step, "avg_launch_us": round(mac_avg_s * 1e6, 3)}
+    fwd_avg_s = kern["ntt_fwd"]["total_ms"] / 1e3 / kern["ntt_fwd"]["launches"]
+    fwd_bfly = st.butterflies_fwd() / n_layers          # one forward launch per layer
+    fwd_g = fwd_bfly / fwd_avg_s / 1e9
+    roof_fwd = {"bound": "alu", "achieved": round(fwd_g, 1), "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s",
+                "frac": round(fwd_g / BFLY_PEAK_G, 4), "traffic": pmc_traffic("ntt_fwd"),
+                "butterflies_per_launch": int(fwd_bfly), "kernel": "k_ntt_fwd (forward negacyclic NTT)",
+                "launches_per_step": n_layers, "avg_launch_us": round(fwd_avg_s * 1e6, 3)}
+    per_step = {k: v["total_ms"] for k, v in kern.items()}
+    dominant = max(per_step, key=per_step.get)
+    roofline = roof_fwd if dominant == "ntt_fwd" else roof_mac
     layers_per_s = n_layers * args.steps / T_plain
     graph_lps = n_layers * args.steps / T_graph
     result = {
@@ -285,11 +333,9 @@ def main():
                    "N": 8192, "limbs": 4, "t": wl.T_PLAIN, "layers": n_layers, "images_per_step": 1,
                    "form": "plain: native runtime issues the 20 layer calls back to back on one stream"},
         "limb_poly_macs_per_s": round(st.modmuls() / 8192 * args.steps / T_plain, 1),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_mac_class / k_mac_full (coefficient-wise MAC)",
-                     "algorithmic_bytes_per_step": mac_bytes, "launches_per_step": mac_launches_per_step,
-                     "avg_launch_us": round(mac_avg_s * 1e6, 3)},
+        "roofline": roofline,
+        "roofline_mac": roof_mac,
+        "dominant_kernel": dominant,
         "kernels": kern,
         "forms": {
             "plain": {"layers_per_s": round(layers_per_s, 1), "ms_per_image": round(T_plain / args.steps * 1e3, 4)},
