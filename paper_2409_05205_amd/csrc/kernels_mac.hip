@@ -188,69 +188,24 @@ k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uin
         }
     }
     const uint32_t M = CLASS ? (N >> s_log) : N;
-    if (!CLASS) {
-#pragma unroll
-        for (int i = 0; i < TB_IB; ++i)
-#pragma unroll
-            for (int j = 0; j < TB_NB; ++j) {
-                const uint32_t b = b0 + i, n = n0 + j;
-                if (live && b < B && n < c_o)
-                    *reinterpret_cast<uint2 *>(out + ((size_t)(b * c_o + n) * L + l) * M + k2) =
-                        make_uint2(reduce64(acc[i][j][0], c), reduce64(acc[i][j][NS - 1], c));
-            }
-        return;
-    }
-    // Residue-class form: the P = s/2 lanes of a block hold partial sums of the same
-    // IB x NB outputs.  Reduce-scatter across them: each step exchanges half of the
-    // values a lane still carries with the lane across one mask bit, so a lane ends
-    // with max(16 / P, 1) fully summed outputs (about 17 shuffles instead of 16 log2 P).
-    constexpr int NV = TB_IB * TB_NB;
-    uint32_t v[NV];
 #pragma unroll
     for (int i = 0; i < TB_IB; ++i)
 #pragma unroll
-        for (int j = 0; j < TB_NB; ++j) v[i * TB_NB + j] = reduce64(acc[i][j][0], c);
-    const uint32_t P = (1u << s_log) >> 1;   // lanes per block, 1..64
-    const uint32_t lane = threadIdx.x;
-    uint32_t base = 0;                        // first output index this lane keeps
-    bool writer = true;
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const uint32_t m = P >> (t + 1);
-        if (m == 0) break;                    // uniform: P is the same for every lane
-        const bool upper = (lane & m) != 0;
-        constexpr int dummy = 0;
-        (void)dummy;
-        const int nv = (NV >> t) > 1 ? (NV >> t) : 1;
-        if (nv > 1) {
-            const int half = nv >> 1;
-#pragma unroll
-            for (int i = 0; i < NV / 2; ++i) {
-                if (i >= half) break;
-                const uint32_t send = upper ? v[i] : v[i + half];
-                const uint32_t keep = upper ? v[i + half] : v[i];
-                const uint32_t recv = (uint32_t)__shfl_xor((int)send, (int)m);
-                v[i] = addmod(keep, recv, c.q);
+        for (int j = 0; j < TB_NB; ++j) {
+            const uint32_t b = b0 + i, n = n0 + j;
+            const bool mine = live && b < B && n < c_o;
+            uint32_t *dst = out + ((size_t)(b * c_o + n) * L + l) * M;
+            if (!CLASS) {
+                if (mine)
+                    *reinterpret_cast<uint2 *>(dst + k2) =
+                        make_uint2(reduce64(acc[i][j][0], c), reduce64(acc[i][j][NS - 1], c));
+            } else {
+                uint32_t v = reduce64(acc[i][j][0], c);
+                const uint32_t lanes = (1u << s_log) >> 1;   // lanes per block (<= 64)
+                for (uint32_t m = 1; m < lanes; m <<= 1) v = addmod(v, (uint32_t)__shfl_xor((int)v, (int)m), c.q);
+                if (mine && (threadIdx.x & (lanes - 1)) == 0) dst[k2 >> s_log] = v;
             }
-            if (upper) base += half;
-        } else {
-            v[0] = addmod(v[0], (uint32_t)__shfl_xor((int)v[0], (int)m), c.q);
-            if (upper) writer = false;
         }
-    }
-    int steps = 0;
-    while ((P >> steps) > 1) ++steps;
-    const int nv_final = (NV >> steps) > 1 ? (NV >> steps) : 1;
-    if (live && writer) {
-        const uint32_t blk = k2 >> s_log;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            if (i >= nv_final) break;
-            const uint32_t e = base + i;
-            const uint32_t b = b0 + e / TB_NB, n = n0 + e % TB_NB;
-            if (b < B && n < c_o) out[((size_t)(b * c_o + n) * L + l) * M + blk] = v[i];
-        }
-    }
 }
 
 __device__ __forceinline__ uint32_t mul_delta(uint32_t m, const LimbConst &c) {
