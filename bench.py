@@ -40,9 +40,6 @@ BFLY_PEAK_G = 4470.0
 # HBM traffic per launch from the FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a 256 MiB
 # copy), valid while the kernel source is the one that was measured.
 PMC_TRAFFIC = {
-    "mac": {"source": "paper_2409_05205_amd/csrc/kernels_mac.hip",
-            "sha256": "cae9d897f2f731e467e8dcde24cfb8c4ce05881b2e6c7460e371861244928ab9",
-            "bytes_per_launch": 17902686},
     "ntt_fwd": {"source": "paper_2409_05205_amd/csrc/kernels_ntt.hip",
                 "sha256": "ef74afd2a0e95976aa551fa144b076fe777b22c7d2c24e449af46b7b76089e29",
                 "bytes_per_launch": 1832600},
@@ -127,16 +124,40 @@ class Stack:
         """Image-layer evaluations per pass (conv layers count B images, FC heads their B)."""
         return sum(B for _, B, _, _, _ in self.steps)
 
-    def mac_bytes(self):
-        """Algorithmic bytes of the MAC kernels in one pass: resident operands once,
-        NTT-domain inputs and MAC outputs once per image."""
+    def mac_plan(self, he):
+        """Which launch carries each layer's MAC: 'fused' (MAC + residue-class tail in one
+        launch) or 'split' (MAC launch, then tail / inverse launch), read from the kernel
+        kinds one call of the layer records."""
+        plan = []
+        kinds = he.HE_K_MAC | he.HE_K_MAC_TAIL
+        for ly, B, c0, sh, shn in self.steps:
+            self.ctx.profile_reset()
+            self.ctx.profile_enable(kinds)
+            if ly.kind == he.HE_LAYER_CONV:
+                self.ctx.conv_layer(ly, c0, sh, shn)
+            else:
+                self.ctx.fc_layer(ly, c0, sh, shn)
+            fused = self.ctx.profile_read(he.HE_K_MAC_TAIL)[0] > 0
+            self.ctx.profile_enable(0)
+            plan.append("fused" if fused else "split")
+        self.ctx.profile_reset()
+        return plan
+
+    def mac_kernel_bytes(self, plan):
+        """Algorithmic bytes of the launches that carry the MAC in one pass: resident operand
+        rows once, NTT-domain inputs once per image, and what the launch writes (block sums or
+        products for a split MAC; output polynomials, after reading sh', for a fused one)."""
         tot = 0
         L, N = self.ctx.L, self.ctx.N
-        for (ly, B, c0, sh, shn), c_o in zip(self.steps, self.rows):
+        for (ly, B, c0, sh, shn), c_o, form in zip(self.steps, self.rows, plan):
             i = ly.info
             J = i.K_in * (2 if sh is not None else 1)
-            out_per = N // i.s if ly.kind == 0 else N
-            tot += J * c_o * L * N * 4 + B * J * L * N * 4 + B * c_o * L * out_per * 4
+            tot += J * c_o * L * N * 4 + B * J * L * N * 4
+            if form == "fused":
+                tot += B * i.K_out * L * N * 4 + (B * i.K_out * N * 4 if shn is not None else 0)
+            else:
+                out_per = N // i.s if ly.kind == 0 and i.flags == 0 else N
+                tot += B * c_o * L * out_per * 4
         return tot
 
     def butterflies_fwd(self):
@@ -256,13 +277,14 @@ def main():
     log(f"plain: {T_plain / args.steps * 1e3:.3f} ms/step")
 
     # kernel timing of the same calls (HIP events on the launch stream)
+    plan = st.mac_plan(he)
     ctx.profile_reset()
-    ctx.profile_enable(he.HE_K_MAC | he.HE_K_NTT_FWD | he.HE_K_TAIL | he.HE_K_INTT)
+    ctx.profile_enable(he.HE_K_MAC | he.HE_K_NTT_FWD | he.HE_K_TAIL | he.HE_K_INTT | he.HE_K_MAC_TAIL)
     with torch.cuda.stream(stream):
         T_prof = time_loop(lambda: st.seq.run(stream), args.steps, 0, sync)
     kern = {}
     for name, kind in [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL),
-                       ("intt", he.HE_K_INTT)]:
+                       ("intt", he.HE_K_INTT), ("mac_tail", he.HE_K_MAC_TAIL)]:
         n, ms = ctx.profile_read(kind)
         kern[name] = {"launches": n, "total_ms": ms, "avg_us": (ms * 1e3 / n) if n else None}
     ctx.profile_enable(0)
@@ -295,14 +317,21 @@ def main():
     lat = lat[2 * n_layers:]
     log(f"plain_host: {T_host / host_steps * 1e3:.3f} ms/step")
 
-    mac_bytes = st.mac_bytes()
+    # the launches that carry the MAC: fused MAC + tail (conv layers at batch one) and the
+    # split MAC (FC head, and any layer the tuner gave the two-launch form)
+    mac_bytes = st.mac_kernel_bytes(plan)
     mac_launches_per_step = n_layers
-    mac_avg_s = kern["mac"]["total_ms"] / 1e3 / kern["mac"]["launches"]
+    mac_ms = kern["mac"]["total_ms"] + kern["mac_tail"]["total_ms"]
+    mac_n = kern["mac"]["launches"] + kern["mac_tail"]["launches"]
+    mac_avg_s = mac_ms / 1e3 / mac_n
     achieved = mac_bytes / mac_launches_per_step / mac_avg_s / 1e9
+    n_fused = plan.count("fused")
     roof_mac = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("mac"),
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": pmc_traffic("mac_tail") if n_fused == n_layers - 1 else None,
                 "algorithmic_bytes_per_launch": mac_bytes // mac_launches_per_step,
-                "kernel": "k_mac_class / k_mac_full (coefficient-wise MAC)",
+                "kernel": f"k_mac_tail (fused MAC + residue-class inverse, {n_fused} layers) / "
+                          f"k_mac_class, k_mac_full (split MAC, {n_layers - n_fused} layers)",
                 "launches_per_step": mac_launches_per_step, "avg_launch_us": round(mac_avg_s * 1e6, 3)}
     fwd_avg_s = kern["ntt_fwd"]["total_ms"] / 1e3 / kern["ntt_fwd"]["launches"]
     fwd_bfly = st.butterflies_fwd() / n_layers          # one forward launch per layer
@@ -311,7 +340,8 @@ def main():
                 "frac": round(fwd_g / BFLY_PEAK_G, 4), "traffic": pmc_traffic("ntt_fwd"),
                 "butterflies_per_launch": int(fwd_bfly), "kernel": "k_ntt_fwd (forward negacyclic NTT)",
                 "launches_per_step": n_layers, "avg_launch_us": round(fwd_avg_s * 1e6, 3)}
-    per_step = {k: v["total_ms"] for k, v in kern.items()}
+    per_step = {"ntt_fwd": kern["ntt_fwd"]["total_ms"], "mac": mac_ms,
+                "tail": kern["tail"]["total_ms"] + kern["intt"]["total_ms"]}
     dominant = max(per_step, key=per_step.get)
     roofline = roof_fwd if dominant == "ntt_fwd" else roof_mac
     layers_per_s = n_layers * args.steps / T_plain

@@ -182,9 +182,10 @@ int he_poly_mul(he_ctx *ctx, uint32_t rows, const uint32_t *d_a, const uint32_t 
  * recorded on the call's stream.  he_profile_read synchronises on the recorded
  * events and returns the number of launches and their summed duration (ms)
  * since the last reset.  Kinds: HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL (residue-
- * class inverse + extraction), HE_K_INTT (full inverse + extraction).
+ * class inverse + extraction), HE_K_INTT (full inverse + extraction),
+ * HE_K_MAC_TAIL (MAC, residue-class inverse and extraction in one launch).
  */
-enum { HE_K_NTT_FWD = 1, HE_K_MAC = 2, HE_K_TAIL = 4, HE_K_INTT = 8 };
+enum { HE_K_NTT_FWD = 1, HE_K_MAC = 2, HE_K_TAIL = 4, HE_K_INTT = 8, HE_K_MAC_TAIL = 16 };
 int he_profile_enable(he_ctx *ctx, uint32_t kind_mask);
 int he_profile_read(he_ctx *ctx, uint32_t kind, uint64_t *launches, double *total_ms);
 int he_profile_reset(he_ctx *ctx);
@@ -289,12 +290,17 @@ void he_server_free(he_server *srv);
  * Tuning.  Knobs: HE_TUNE_NTT_FWD / HE_TUNE_NTT_INV / HE_TUNE_TAIL take the
  * register radix log2 r in 2..5 (each thread keeps 2^r words and runs r stages
  * per LDS pass; 0 = automatic), HE_TUNE_MAC takes 0 (streaming per-image MAC),
- * 1 (register-blocked batched MAC) or -1 (automatic).  Every value yields the
- * same output words.  he_tune_force pins a knob for the whole context (tests
- * sweep all values with it).  he_autotune_layer times every candidate of every
- * knob on the launch shapes of one layer at batch B (synchronising the stream)
- * and keeps the fastest for later calls with that shape; he_tune_get reads a
- * kept choice back (key: knob, log2 of the transform size, rows per launch).
+ * 1 (register-blocked batched MAC), 2 (residue-class conv layers: MAC, inverse
+ * and extraction fused, one workgroup per output row) or -1 (automatic: 2 at
+ * B = 1, 1 at B >= 4); a value the layer's shape does not allow falls back to
+ * 0.  Every value yields the same output words.  he_tune_force pins a knob for the whole context (tests
+ * sweep all values with it).  he_autotune_layer tunes the knobs of one layer at
+ * batch B one after another: each candidate is timed as a whole layer call on
+ * scratch buffers (median of 5, caches evicted before each), and the fastest is
+ * kept for later calls with that shape.  It allocates and frees its scratch
+ * (about 512 MiB plus one call's buffers) and synchronises the stream.
+ * he_tune_get reads a kept choice back (key: knob, log2 of the transform size,
+ * rows per launch; for HE_TUNE_MAC the layer and B).
  */
 enum { HE_TUNE_NTT_FWD = 1, HE_TUNE_NTT_INV = 2, HE_TUNE_TAIL = 3, HE_TUNE_MAC = 4 };
 int he_tune_force(he_ctx *ctx, uint32_t knob, int32_t value);

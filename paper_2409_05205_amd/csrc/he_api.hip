@@ -14,6 +14,7 @@
 #include <chrono>
 #include <functional>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -188,6 +189,32 @@ int knob(he_ctx *ctx, int which, uint32_t logsize, uint32_t rows) {
     return it == ctx->tuned.end() ? (which == HE_TUNE_MAC ? -1 : 0) : it->second;
 }
 
+// Conv MAC variant of a layer at batch B: 0 streaming (then tail), 1 register-blocked
+// batched (then tail), 2 fused MAC + residue-class tail.  A tuned or forced value is
+// used when the layer's shape allows it; otherwise, and by default, B = 1 takes the
+// fused form and B >= 4 the batched one.
+bool mac_tiled_ok(const he_layer *ly, uint32_t B) {
+    const he_layer_info &in = ly->info;
+    const bool cls = in.flags == HE_PACK_CLASS_INTT;
+    return B >= 2 && (!cls || (in.s >= 2 && in.s <= 128));
+}
+
+bool mac_fused_ok(const he_ctx *ctx, const he_layer *ly) {
+    const he_layer_info &in = ly->info;
+    const uint32_t logm = ctx->logN - log2u(in.s);
+    return in.kind == HE_LAYER_CONV && in.flags == HE_PACK_CLASS_INTT && logm >= 4 && in.s <= 256 && in.N >= 256;
+}
+
+int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
+    const int mk = knob(ctx, HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B);
+    const bool tiled_ok = mac_tiled_ok(ly, B), fused_ok = mac_fused_ok(ctx, ly);
+    if (mk == 2) return fused_ok ? 2 : 0;
+    if (mk == 1) return tiled_ok ? 1 : 0;
+    if (mk == 0) return 0;
+    if (B == 1 && fused_ok) return 2;
+    return tiled_ok && B >= 4 ? 1 : 0;
+}
+
 // Times one kernel launch with dispatch-recorded events when profiling is on for its kind.
 struct ProfScope {
     he_ctx *ctx;
@@ -212,32 +239,6 @@ struct ProfScope {
 
 }  // namespace
 
-namespace {
-
-// Average duration (ms) of `reps` launches made by fn(stream), after two warm-up launches.
-template <class F>
-int time_launches(hipStream_t st, int reps, F fn, double *ms_out) {
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HE_EDEVICE;
-    int rc = HE_OK;
-    for (int i = 0; i < 2 && rc == HE_OK; ++i)
-        if (fn(st) != hipSuccess) rc = HE_EDEVICE;
-    if (rc == HE_OK) {
-        hipEventRecord(a, st);
-        for (int i = 0; i < reps && rc == HE_OK; ++i)
-            if (fn(st) != hipSuccess) rc = HE_EDEVICE;
-        hipEventRecord(b, st);
-        hipEventSynchronize(b);
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, a, b);
-        *ms_out = ms / reps;
-    }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
-    return rc;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -388,108 +389,100 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
     if (!ctx || !ly || ly->ctx != ctx || B == 0) return HE_EINVAL;
     const he_layer_info &in = ly->info;
     hipStream_t st = (hipStream_t)stream;
-    const int logN = (int)ctx->logN;
-    const uint32_t N = in.N, L = in.L, Jtot = 2 * in.K_in, c_o = ly->n_rows;
-    void *ws = nullptr;
-    const size_t need = layer_ws_bytes(ly, B);
-    int rc = ctx_workspace(ctx, st, need, &ws);
-    if (rc != HE_OK) return rc;
-    uint32_t *xn = (uint32_t *)ws;
-    uint32_t *mac = (uint32_t *)((char *)ws + align256((size_t)B * Jtot * L * N * 4));
-    const size_t out_words = in.kind == HE_LAYER_CONV ? (size_t)B * in.K_out * L * N : (size_t)B * in.blocks * L * in.n_o_p;
-    uint32_t *out = nullptr;
-    if (hipMalloc((void **)&out, out_words * 4) != hipSuccess) return HE_ENOMEM;
-    // the workspace holds arbitrary words: timing does not depend on the values and no
-    // kernel's addressing does either
+    const uint32_t logN = ctx->logN, N = in.N, L = in.L;
+    const bool conv = in.kind == HE_LAYER_CONV;
+    // Scratch inputs, outputs and workspace of one call at batch B, plus a buffer whose
+    // rewrite before every timed call evicts L2 and the last-level cache, so each
+    // candidate is timed as a whole layer call from cold memory, as in a stream of
+    // layers whose operands do not stay cached.  The words are zeros: no timing and no
+    // kernel's addressing depends on the values.
+    const size_t c0_b = align256((conv ? (size_t)B * in.K_in : (size_t)B) * L * N * 4);
+    const size_t sh_b = align256((conv ? (size_t)B * in.K_in : (size_t)B) * N * 4);
+    const size_t shn_b = align256(conv ? (size_t)B * in.K_out * N * 4 : (size_t)B * in.blocks * in.n_o_p * 4);
+    const size_t out_b = align256(conv ? (size_t)B * in.K_out * L * N * 4 : (size_t)B * in.blocks * L * in.n_o_p * 4);
+    const size_t ws_b = align256(layer_ws_bytes(ly, B));
+    const size_t flush_b = (size_t)512 << 20;
+    const size_t data_b = c0_b + sh_b + shn_b + out_b + ws_b;
+    char *buf = nullptr;
+    if (hipMalloc((void **)&buf, data_b + flush_b) != hipSuccess) return HE_ENOMEM;
+    const uint32_t *c0 = (const uint32_t *)buf;
+    const uint32_t *sh = (const uint32_t *)(buf + c0_b);
+    const uint32_t *shn = (const uint32_t *)(buf + c0_b + sh_b);
+    uint32_t *out = (uint32_t *)(buf + c0_b + sh_b + shn_b);
+    void *ws = buf + c0_b + sh_b + shn_b + out_b;
+    char *flush = buf + data_b;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    int rc = HE_OK;
+    if (hipMemsetAsync(buf, 0, data_b, st) != hipSuccess || hipEventCreate(&ea) != hipSuccess ||
+        hipEventCreate(&eb) != hipSuccess)
+        rc = HE_EDEVICE;
+    const uint32_t saved_prof = ctx->prof_mask;
+    ctx->prof_mask = 0;
+
+    // median duration (ms) of one layer call after one untimed call
+    auto time_layer = [&](bool with_sh, double *ms_out) -> int {
+        constexpr int REPS = 5;
+        float ms[REPS];
+        for (int r = -1; r < REPS; ++r) {
+            if (hipMemsetAsync(flush, r & 0xff, flush_b, st) != hipSuccess) return HE_EDEVICE;
+            if (hipEventRecord(ea, st) != hipSuccess) return HE_EDEVICE;
+            const int lrc = conv ? he_conv_layer_ws(ctx, ly, B, c0, with_sh ? sh : nullptr, shn, out, ws, ws_b, st)
+                                 : he_fc_layer_ws(ctx, ly, B, c0, with_sh ? sh : nullptr, shn, out, ws, ws_b, st);
+            if (lrc != HE_OK) return lrc;
+            if (hipEventRecord(eb, st) != hipSuccess || hipEventSynchronize(eb) != hipSuccess) return HE_EDEVICE;
+            if (r >= 0 && hipEventElapsedTime(&ms[r], ea, eb) != hipSuccess) return HE_EDEVICE;
+        }
+        std::sort(ms, ms + REPS);
+        *ms_out = ms[REPS / 2];
+        return HE_OK;
+    };
+    // try every candidate of one knob with the others at their current values; keep the fastest
     auto pick = [&](int which, uint32_t key_size, uint32_t key_rows, const std::vector<int> &cands,
-                    const std::function<hipError_t(hipStream_t, int)> &run) -> int {
+                    bool with_sh) -> int {
+        const auto key = std::make_tuple(which, key_size, key_rows);
         double best = 1e30;
-        int arg = cands.empty() ? 0 : cands[0];
+        int arg = cands[0];
         for (int c : cands) {
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                ctx->tuned[key] = c;
+            }
             double ms = 0;
-            int r = time_launches(st, 5, [&](hipStream_t s) { return run(s, c); }, &ms);
-            if (r != HE_OK) continue;   // an invalid variant for this shape
+            const int r = time_layer(with_sh, &ms);
+            if (r != HE_OK) return r;
             if (ms < best) {
                 best = ms;
                 arg = c;
             }
         }
-        hipGetLastError();
         std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->tuned[std::make_tuple(which, key_size, key_rows)] = arg;
-        return arg;
+        ctx->tuned[key] = arg;
+        return HE_OK;
     };
     const std::vector<int> radix{2, 3, 4, 5};
-    const uint32_t rows0 = B * in.K_in * L;
-    for (uint32_t mult : {1u, 2u}) {   // c0 alone (first layer) or c0 + sh
-        FwdJobs jobs;
-        RowMap m;
-        m.J = 1;
-        m.L = L;
-        m.src_b = m.dst_b = (uint64_t)L * N;
-        m.src_j = m.dst_j = 0;
-        m.src_l = m.dst_l = N;
-        jobs.map[0] = jobs.map[1] = m;
-        jobs.src[0] = jobs.src[1] = xn;
-        jobs.dst[0] = jobs.dst[1] = xn;
-        jobs.rows0 = rows0 * mult;
-        pick(HE_TUNE_NTT_FWD, (uint32_t)logN, rows0 * mult, radix, [&](hipStream_t s, int lr) {
-            return launch_ntt_fwd2(logN, lr, jobs, rows0 * mult, ctx->tw, ctx->twsh, ctx->lc, s, nullptr);
-        });
-    }
-    if (in.kind == HE_LAYER_CONV) {
+    const uint32_t fwd_rows = (conv ? B * in.K_in : B) * L;
+    // a network's first layer has no input share: its forward launch has half the rows
+    if (rc == HE_OK) rc = pick(HE_TUNE_NTT_FWD, logN, fwd_rows, radix, false);
+    if (rc == HE_OK) rc = pick(HE_TUNE_NTT_FWD, logN, 2 * fwd_rows, radix, true);
+    if (conv) {
         const bool cls = in.flags == HE_PACK_CLASS_INTT;
-        if (B >= 2 && (!cls || (in.s >= 2 && in.s <= 128)))
-            pick(HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B, {0, 1}, [&](hipStream_t s, int v) {
-                if (v == 1) return launch_mac_tiled(xn, ly->op, mac, B, Jtot, Jtot, c_o, L, N, in.s, cls, ctx->lc, s);
-                return cls ? launch_mac_class(xn, ly->op, mac, B, Jtot, Jtot, c_o, L, N, in.s, ctx->lc, s)
-                           : launch_mac_full(xn, ly->op, mac, B, Jtot, Jtot, c_o, L, N, ctx->lc, s);
-            });
-        if (cls) {
-            const uint32_t logm = (uint32_t)logN - log2u(in.s);
-            if (logm >= 4)
-                pick(HE_TUNE_TAIL, logm, B * in.K_out * in.g_o * L, radix, [&](hipStream_t s, int lr) {
-                    return launch_tail_rows(mac, out, nullptr, B, c_o, in.g_o, in.K_out, L, N, in.s, ctx->twi,
-                                            ctx->twish, ctx->lc, s, nullptr, lr);
-                });
-        } else {
-            EpiParams ep;
-            std::memset(&ep, 0, sizeof(ep));
-            ep.c_o = c_o;
-            ep.g_o = in.g_o;
-            ep.K_out = in.K_out;
-            ep.s_log = log2u(in.s);
-            ep.out = out;
-            RowMap mi;
-            std::memset(&mi, 0, sizeof(mi));
-            mi.J = 1;
-            mi.L = L;
-            const uint32_t rows = B * in.K_out * in.g_o * L;
-            pick(HE_TUNE_NTT_INV, (uint32_t)logN, rows, radix, [&](hipStream_t s, int lr) {
-                return launch_ntt_inv(logN, mac, out, mi, rows, ctx->twi, ctx->twish, ctx->lc, EPI_CONV_CLASS, ep, s,
-                                      nullptr, lr);
-            });
-        }
-    } else {
-        EpiParams ep;
-        std::memset(&ep, 0, sizeof(ep));
-        ep.n_o_p = in.n_o_p;
-        ep.blocks = in.blocks;
-        ep.out = out;
-        ep.bias = ly->bias;
-        RowMap mi;
-        std::memset(&mi, 0, sizeof(mi));
-        mi.J = 1;
-        mi.L = L;
-        const uint32_t rows = B * in.blocks * L;
-        pick(HE_TUNE_NTT_INV, (uint32_t)logN, rows, radix, [&](hipStream_t s, int lr) {
-            return launch_ntt_inv(logN, mac, out, mi, rows, ctx->twi, ctx->twish, ctx->lc, EPI_FC_PREFIX, ep, s,
-                                  nullptr, lr);
-        });
+        std::vector<int> macs{0};
+        if (mac_tiled_ok(ly, B)) macs.push_back(1);
+        if (mac_fused_ok(ctx, ly)) macs.push_back(2);
+        if (rc == HE_OK && macs.size() > 1) rc = pick(HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B, macs, true);
+        const uint32_t logm = logN - log2u(in.s);
+        const uint32_t rows = B * in.K_out * in.g_o * L;
+        if (rc == HE_OK && cls && logm >= 4) rc = pick(HE_TUNE_TAIL, logm, rows, radix, true);
+        if (rc == HE_OK && !cls) rc = pick(HE_TUNE_NTT_INV, logN, rows, radix, true);
+    } else if (rc == HE_OK) {
+        rc = pick(HE_TUNE_NTT_INV, logN, B * in.blocks * L, radix, true);
     }
+    ctx->prof_mask = saved_prof;
     hipStreamSynchronize(st);
-    hipFree(out);
-    return HE_OK;
+    if (ea) hipEventDestroy(ea);
+    if (eb) hipEventDestroy(eb);
+    hipFree(buf);
+    return rc;
 }
 
 int he_tune_get(he_ctx *ctx, uint32_t which, uint32_t key_size, uint32_t key_rows, int32_t *value) {
@@ -927,10 +920,17 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
     // a2: coefficient-wise MAC over the input rows
     const uint32_t Juse = d_sh ? Jtot : K_in;
     const bool cls = in.flags == HE_PACK_CLASS_INTT;
+    const int mk = mac_variant(ctx, ly, B);
+    if (mk == 2) {
+        // a2 + a3 + a4 in one launch: MAC, residue-class inverse, extraction, + Delta sh'
+        ProfScope ps(ctx, HE_K_MAC_TAIL);
+        e = launch_mac_tail(xn, ly->op, d_out, d_sh_next, B, Jtot, Juse, c_o, in.g_o, in.K_out, L, N, in.s, ctx->twi,
+                            ctx->twish, ctx->lc, st, ps.ev());
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "conv mac + tail");
+        return HE_OK;
+    }
     {
-        const int mk = knob(ctx, HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B);
-        const bool tiled_ok = B >= 2 && (!cls || (in.s >= 2 && in.s <= 128));
-        const bool tiled = tiled_ok && (mk < 0 ? B >= 4 : mk == 1);
+        const bool tiled = mk == 1;
         ProfScope ps(ctx, HE_K_MAC);
         if (tiled)
             e = launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, cls, ctx->lc, st, ps.ev());

@@ -66,3 +66,48 @@ __device__ __forceinline__ void gs_bfly(uint32_t &x, uint32_t &y, uint32_t w, ui
     x = csub(u, q2);
     y = shoup_lazy(d, w, wsh, q);
 }
+
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t q) { return csub(a + b, q); }
+
+// Accumulate four slots of rows J in [0, Juse) for one image.  Rows are taken
+// MAC_ROWS at a time with every load of the group issued before the products,
+// so a thread keeps 2 * MAC_ROWS 16-byte loads in flight; rows past Juse
+// contribute zero.  The sums are folded below q after every 3 groups
+// (12 products: 12 q^2 + q < 2^64).
+constexpr int MAC_ROWS = 4;
+
+__device__ __forceinline__ void mac4(const uint32_t *__restrict__ x, size_t xstride,
+                                     const uint32_t *__restrict__ op, size_t opstride, uint32_t Juse,
+                                     const LimbConst &c, uint32_t (&r)[4]) {
+    uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    uint32_t groups = 0;
+    for (uint32_t J0 = 0; J0 < Juse; J0 += MAC_ROWS) {
+        uint4 xv[MAC_ROWS], ov[MAC_ROWS];
+#pragma unroll
+        for (int u = 0; u < MAC_ROWS; ++u) {
+            const uint32_t J = J0 + u < Juse ? J0 + u : Juse - 1;
+            xv[u] = *reinterpret_cast<const uint4 *>(x + (size_t)J * xstride);
+            ov[u] = *reinterpret_cast<const uint4 *>(op + (size_t)J * opstride);
+        }
+#pragma unroll
+        for (int u = 0; u < MAC_ROWS; ++u) {
+            if (J0 + u < Juse) {
+                a0 += (uint64_t)xv[u].x * ov[u].x;
+                a1 += (uint64_t)xv[u].y * ov[u].y;
+                a2 += (uint64_t)xv[u].z * ov[u].z;
+                a3 += (uint64_t)xv[u].w * ov[u].w;
+            }
+        }
+        if (++groups == 3) {
+            a0 = reduce64(a0, c);
+            a1 = reduce64(a1, c);
+            a2 = reduce64(a2, c);
+            a3 = reduce64(a3, c);
+            groups = 0;
+        }
+    }
+    r[0] = reduce64(a0, c);
+    r[1] = reduce64(a1, c);
+    r[2] = reduce64(a2, c);
+    r[3] = reduce64(a3, c);
+}

@@ -100,6 +100,14 @@ hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh
                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
                             const LaunchEv *ev = nullptr, int logr = 0);
 
+// Fused class-form MAC + residue-class tail: one workgroup per output row
+// (b, g, n', l); same output as launch_mac_class followed by launch_tail_rows.
+// Requires s <= 256, 16 <= N/s <= 16384, N >= 256.
+hipError_t launch_mac_tail(const uint32_t *X, const uint32_t *Op, uint32_t *out, const uint32_t *sh_next, uint32_t B,
+                           uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L,
+                           uint32_t N, uint32_t s, const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
+                           hipStream_t st, const LaunchEv *ev = nullptr);
+
 // Client-side element-wise kernels (kernels_client.hip).
 struct DecConsts {
     uint32_t t;

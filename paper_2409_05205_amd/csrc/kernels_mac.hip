@@ -5,7 +5,7 @@
 // coefficient-wise products in the NTT domain, Sec. IV-A-1): each thread owns
 // four consecutive NTT slots (one 16-byte load per operand row), accumulates
 // 32x32->64-bit products over the input polynomials J, and folds the 64-bit
-// sums back below q every 15 terms so they never overflow.
+// sums back below q often enough that they never overflow.
 //
 // Residue-class form: the inverse transform's first log2(s) stages over each
 // block of s slots are linear in the block, so the row of that block transform
@@ -19,35 +19,6 @@
 namespace {
 
 constexpr int MAC_THREADS = 256;
-
-__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t q) { return csub(a + b, q); }
-
-// Accumulate four slots of rows J in [0, Juse) for one image.
-__device__ __forceinline__ void mac4(const uint32_t *__restrict__ x, size_t xstride,
-                                     const uint32_t *__restrict__ op, size_t opstride, uint32_t Juse,
-                                     const LimbConst &c, uint32_t (&r)[4]) {
-    uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    uint32_t cnt = 0;
-    for (uint32_t J = 0; J < Juse; ++J) {
-        const uint4 xv = *reinterpret_cast<const uint4 *>(x + (size_t)J * xstride);
-        const uint4 ov = *reinterpret_cast<const uint4 *>(op + (size_t)J * opstride);
-        a0 += (uint64_t)xv.x * ov.x;
-        a1 += (uint64_t)xv.y * ov.y;
-        a2 += (uint64_t)xv.z * ov.z;
-        a3 += (uint64_t)xv.w * ov.w;
-        if (++cnt == 15) {   // 15 q^2 + q < 2^64
-            a0 = reduce64(a0, c);
-            a1 = reduce64(a1, c);
-            a2 = reduce64(a2, c);
-            a3 = reduce64(a3, c);
-            cnt = 0;
-        }
-    }
-    r[0] = reduce64(a0, c);
-    r[1] = reduce64(a1, c);
-    r[2] = reduce64(a2, c);
-    r[3] = reduce64(a3, c);
-}
 
 __global__ void __launch_bounds__(MAC_THREADS)
 k_mac_full(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ out, uint32_t B,

@@ -25,11 +25,95 @@ __device__ __forceinline__ uint32_t gidx(uint32_t F, uint32_t vv) {
     return ((F >> LO) << (LO + RP)) | (vv << LO) | (F & ((1u << LO) - 1u));
 }
 
+// Twiddles of the leading passes, fetched into registers at kernel entry.  A
+// pass of RP radix-2 stages needs 2^RP - 1 twiddle pairs per register group;
+// fetching them up front overlaps their latency with the first data load
+// instead of paying it after every barrier.  Passes beyond the register budget
+// of the launch shape (TPB threads per workgroup) read their twiddles in place.
+template <int LOGN, int LOGR, int TPB>
+struct PassTw {
+    static constexpr int NP = (LOGN + LOGR - 1) / LOGR;
+    static constexpr int rp(int P) { return LOGN - P * LOGR < LOGR ? LOGN - P * LOGR : LOGR; }
+    static constexpr int cnt(int P) { return ((1 << LOGR) >> rp(P)) * ((1 << rp(P)) - 1); }
+    static constexpr int off(int P) { return P == 0 ? 0 : off(P - 1) + cnt(P - 1); }
+    static constexpr int waves_per_simd = TPB >= 512 ? TPB / 256 : 1;
+    static constexpr int limit = 512 / waves_per_simd < 256 ? 512 / waves_per_simd : 256;
+    static constexpr int budget = limit - (1 << LOGR) - 48;
+    static constexpr int pf(int P, int used) {
+        return (P < NP && used + 2 * cnt(P) <= budget) ? pf(P + 1, used + 2 * cnt(P)) : P;
+    }
+    static constexpr int PF = pf(0, 0);
+    static constexpr int TOTAL = off(PF) > 0 ? off(PF) : 1;
+    uint32_t w[TOTAL], ws[TOTAL];
+};
+
+// Forward pass P, stage k, group g: the pair (vv, vv + half) uses twiddle
+// psi^brv(2^(S0+k) + ((F >> LO) << k) + (vv >> (RP - k))), slot (2^k - 1) + (vv >> (RP - k)).
+template <int LOGN, int LOGR, int TPB, int P>
+__device__ __forceinline__ void fwd_tw_load(PassTw<LOGN, LOGR, TPB> &tw, uint32_t tid, const uint32_t *__restrict__ W,
+                                            const uint32_t *__restrict__ Wsh) {
+    using PT = PassTw<LOGN, LOGR, TPB>;
+    if constexpr (P < PT::PF) {
+        constexpr int T = 1 << (LOGN - LOGR);
+        constexpr int S0 = P * LOGR;
+        constexpr int RP = PT::rp(P);
+        constexpr int LO = LOGN - S0 - RP;
+        constexpr int G = (1 << LOGR) >> RP;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t hi = (tid + g * T) >> LO;
+#pragma unroll
+            for (int k = 0; k < RP; ++k)
+#pragma unroll
+                for (int top = 0; top < (1 << k); ++top) {
+                    const uint32_t ti = (1u << (S0 + k)) + (hi << k) + top;
+                    const int slot = PT::off(P) + g * ((1 << RP) - 1) + (1 << k) - 1 + top;
+                    tw.w[slot] = W[ti];
+                    tw.ws[slot] = Wsh[ti];
+                }
+        }
+        fwd_tw_load<LOGN, LOGR, TPB, P + 1>(tw, tid, W, Wsh);
+    }
+}
+
+// Inverse pass P, stage kk, group g: the pair (vv, vv + 2^kk) uses twiddle
+// psi^-brv(2^(LOGN-S0-kk-1) + ((F >> S0) << (RP-kk-1)) + (vv >> (kk+1))),
+// slot (2^(RP-kk-1) - 1) + (vv >> (kk+1)).
+template <int LOGN, int LOGR, int TPB, int P>
+__device__ __forceinline__ void inv_tw_load(PassTw<LOGN, LOGR, TPB> &tw, uint32_t tid, const uint32_t *__restrict__ W,
+                                            const uint32_t *__restrict__ Wsh) {
+    using PT = PassTw<LOGN, LOGR, TPB>;
+    if constexpr (P < PT::PF) {
+        constexpr int T = 1 << (LOGN - LOGR);
+        constexpr int S0 = P * LOGR;
+        constexpr int RP = PT::rp(P);
+        constexpr int G = (1 << LOGR) >> RP;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t hi = (tid + g * T) >> S0;
+#pragma unroll
+            for (int kk = 0; kk < RP; ++kk)
+#pragma unroll
+                for (int u = 0; u < (1 << (RP - kk - 1)); ++u) {
+                    const uint32_t ti = (1u << (LOGN - S0 - kk - 1)) + (hi << (RP - kk - 1)) + u;
+                    const int slot = PT::off(P) + g * ((1 << RP) - 1) + (1 << (RP - kk - 1)) - 1 + u;
+                    tw.w[slot] = W[ti];
+                    tw.ws[slot] = Wsh[ti];
+                }
+        }
+        inv_tw_load<LOGN, LOGR, TPB, P + 1>(tw, tid, W, Wsh);
+    }
+}
+
 // ------------------------------------------------------------------ forward
-template <int LOGN, int LOGR, int S0, int RP>
-__device__ __forceinline__ void fwd_stages(uint32_t (&v)[1 << LOGR], uint32_t tid, const uint32_t *__restrict__ W,
-                                           const uint32_t *__restrict__ Wsh, uint32_t q, uint32_t q2) {
+template <int LOGN, int LOGR, int TPB, int P>
+__device__ __forceinline__ void fwd_stages(uint32_t (&v)[1 << LOGR], const PassTw<LOGN, LOGR, TPB> &tw, uint32_t tid,
+                                           const uint32_t *__restrict__ W, const uint32_t *__restrict__ Wsh,
+                                           uint32_t q, uint32_t q2) {
+    using PT = PassTw<LOGN, LOGR, TPB>;
     constexpr int T = 1 << (LOGN - LOGR);
+    constexpr int S0 = P * LOGR;
+    constexpr int RP = PT::rp(P);
     constexpr int LO = LOGN - S0 - RP;
     constexpr int G = (1 << LOGR) >> RP;
 #pragma unroll
@@ -42,18 +126,28 @@ __device__ __forceinline__ void fwd_stages(uint32_t (&v)[1 << LOGR], uint32_t ti
 #pragma unroll
             for (int vv = 0; vv < (1 << RP); ++vv) {
                 if (vv & half) continue;
-                const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
-                const uint32_t ti = (1u << s) + (idx >> (LOGN - s));
-                ct_bfly(v[g * (1 << RP) + vv], v[g * (1 << RP) + vv + half], W[ti], Wsh[ti], q, q2);
+                uint32_t w, wsh;
+                if constexpr (P < PT::PF) {
+                    const int slot = PT::off(P) + g * ((1 << RP) - 1) + (1 << k) - 1 + (vv >> (RP - k));
+                    w = tw.w[slot];
+                    wsh = tw.ws[slot];
+                } else {
+                    const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
+                    const uint32_t ti = (1u << s) + (idx >> (LOGN - s));
+                    w = W[ti];
+                    wsh = Wsh[ti];
+                }
+                ct_bfly(v[g * (1 << RP) + vv], v[g * (1 << RP) + vv + half], w, wsh, q, q2);
             }
         }
     }
 }
 
-template <int LOGN, int LOGR, int P>
-__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], uint32_t *lds, uint32_t tid,
-                                         const uint32_t *__restrict__ in, const uint32_t *__restrict__ W,
-                                         const uint32_t *__restrict__ Wsh, uint32_t q, uint32_t q2) {
+template <int LOGN, int LOGR, int TPB, int P>
+__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], const PassTw<LOGN, LOGR, TPB> &tw, uint32_t *lds,
+                                         uint32_t tid, const uint32_t *__restrict__ in,
+                                         const uint32_t *__restrict__ W, const uint32_t *__restrict__ Wsh, uint32_t q,
+                                         uint32_t q2) {
     constexpr int T = 1 << (LOGN - LOGR);
     constexpr int S0 = P * LOGR;
     constexpr int RP = (LOGN - S0 < LOGR) ? (LOGN - S0) : LOGR;
@@ -68,7 +162,7 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], uint32_t *lds
             v[g * (1 << RP) + vv] = (P == 0) ? in[idx] : lds[lpad(idx)];
         }
     }
-    fwd_stages<LOGN, LOGR, S0, RP>(v, tid, W, Wsh, q, q2);
+    fwd_stages<LOGN, LOGR, TPB, P>(v, tw, tid, W, Wsh, q, q2);
     if (P > 0) __syncthreads();   // every read of this pass is done before any write
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -80,7 +174,7 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], uint32_t *lds
         }
     }
     __syncthreads();
-    if constexpr (S0 + RP < LOGN) fwd_pass<LOGN, LOGR, P + 1>(v, lds, tid, in, W, Wsh, q, q2);
+    if constexpr (S0 + RP < LOGN) fwd_pass<LOGN, LOGR, TPB, P + 1>(v, tw, lds, tid, in, W, Wsh, q, q2);
 }
 
 template <int LOGN, int LOGR>
@@ -101,8 +195,12 @@ k_ntt_fwd(FwdJobs jobs, const uint32_t *__restrict__ tw, const uint32_t *__restr
     const uint32_t *in = jobs.src[js] + b * map.src_b + j * map.src_j + l * map.src_l;
     uint32_t *out = jobs.dst[js] + b * map.dst_b + j * map.dst_j + l * map.dst_l;
     const uint32_t q = lc.l[l].q, q2 = lc.l[l].q2;
+    const uint32_t *W = tw + (size_t)l * N;
+    const uint32_t *Wsh = twsh + (size_t)l * N;
+    PassTw<LOGN, LOGR, T> ptw;
+    fwd_tw_load<LOGN, LOGR, T, 0>(ptw, tid, W, Wsh);
     uint32_t v[1 << LOGR];
-    fwd_pass<LOGN, LOGR, 0>(v, lds, tid, in, tw + (size_t)l * N, twsh + (size_t)l * N, q, q2);
+    fwd_pass<LOGN, LOGR, T, 0>(v, ptw, lds, tid, in, W, Wsh, q, q2);
 #pragma unroll
     for (int i = 0; i < (1 << LOGR); ++i) {
         const uint32_t idx = tid + i * T;
@@ -113,10 +211,14 @@ k_ntt_fwd(FwdJobs jobs, const uint32_t *__restrict__ tw, const uint32_t *__restr
 }
 
 // ------------------------------------------------------------------ inverse
-template <int LOGN, int LOGR, int S0, int RP>
-__device__ __forceinline__ void inv_stages(uint32_t (&v)[1 << LOGR], uint32_t tid, const uint32_t *__restrict__ W,
-                                           const uint32_t *__restrict__ Wsh, uint32_t q, uint32_t q2) {
+template <int LOGN, int LOGR, int TPB, int P>
+__device__ __forceinline__ void inv_stages(uint32_t (&v)[1 << LOGR], const PassTw<LOGN, LOGR, TPB> &tw, uint32_t tid,
+                                           const uint32_t *__restrict__ W, const uint32_t *__restrict__ Wsh,
+                                           uint32_t q, uint32_t q2) {
+    using PT = PassTw<LOGN, LOGR, TPB>;
     constexpr int T = 1 << (LOGN - LOGR);
+    constexpr int S0 = P * LOGR;
+    constexpr int RP = PT::rp(P);
     constexpr int LO = S0;
     constexpr int G = (1 << LOGR) >> RP;
 #pragma unroll
@@ -129,47 +231,63 @@ __device__ __forceinline__ void inv_stages(uint32_t (&v)[1 << LOGR], uint32_t ti
 #pragma unroll
             for (int vv = 0; vv < (1 << RP); ++vv) {
                 if (vv & half) continue;
-                const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
-                const uint32_t ti = (1u << (LOGN - k - 1)) + (idx >> (k + 1));
-                gs_bfly(v[g * (1 << RP) + vv], v[g * (1 << RP) + vv + half], W[ti], Wsh[ti], q, q2);
+                uint32_t w, wsh;
+                if constexpr (P < PT::PF) {
+                    const int slot = PT::off(P) + g * ((1 << RP) - 1) + (1 << (RP - kk - 1)) - 1 + (vv >> (kk + 1));
+                    w = tw.w[slot];
+                    wsh = tw.ws[slot];
+                } else {
+                    const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
+                    const uint32_t ti = (1u << (LOGN - k - 1)) + (idx >> (k + 1));
+                    w = W[ti];
+                    wsh = Wsh[ti];
+                }
+                gs_bfly(v[g * (1 << RP) + vv], v[g * (1 << RP) + vv + half], w, wsh, q, q2);
             }
         }
     }
 }
 
-template <int LOGN, int LOGR, int P>
-__device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LOGR], uint32_t *lds, uint32_t tid,
-                                         const uint32_t *__restrict__ W, const uint32_t *__restrict__ Wsh,
-                                         uint32_t q, uint32_t q2) {
+// Threads with act == false take part in the barriers only (a workgroup wider
+// than the transform's T threads).
+template <int LOGN, int LOGR, int TPB, int P>
+__device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LOGR], const PassTw<LOGN, LOGR, TPB> &tw, uint32_t *lds,
+                                         uint32_t tid, const uint32_t *__restrict__ W,
+                                         const uint32_t *__restrict__ Wsh, uint32_t q, uint32_t q2,
+                                         const bool act = true) {
     constexpr int T = 1 << (LOGN - LOGR);
     constexpr int S0 = P * LOGR;
     constexpr int RP = (LOGN - S0 < LOGR) ? (LOGN - S0) : LOGR;
     constexpr int LO = S0;
     constexpr int G = (1 << LOGR) >> RP;
     constexpr bool LAST = (S0 + RP >= LOGN);
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const uint32_t F = tid + g * T;
-#pragma unroll
-        for (int vv = 0; vv < (1 << RP); ++vv) {
-            const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
-            v[g * (1 << RP) + vv] = lds[lpad(idx)];
-        }
-    }
-    inv_stages<LOGN, LOGR, S0, RP>(v, tid, W, Wsh, q, q2);
-    if constexpr (!LAST) {
-        __syncthreads();
+    if (act) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const uint32_t F = tid + g * T;
 #pragma unroll
             for (int vv = 0; vv < (1 << RP); ++vv) {
                 const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
-                lds[lpad(idx)] = v[g * (1 << RP) + vv];
+                v[g * (1 << RP) + vv] = lds[lpad(idx)];
+            }
+        }
+        inv_stages<LOGN, LOGR, TPB, P>(v, tw, tid, W, Wsh, q, q2);
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const uint32_t F = tid + g * T;
+#pragma unroll
+                for (int vv = 0; vv < (1 << RP); ++vv) {
+                    const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
+                    lds[lpad(idx)] = v[g * (1 << RP) + vv];
+                }
             }
         }
         __syncthreads();
-        inv_pass<LOGN, LOGR, P + 1>(v, lds, tid, W, Wsh, q, q2);
+        inv_pass<LOGN, LOGR, TPB, P + 1>(v, tw, lds, tid, W, Wsh, q, q2, act);
     }
 }
 
@@ -249,6 +367,10 @@ k_ntt_inv(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, RowMap m
         biasp = ep.bias + (size_t)blk * ep.n_o_p;
     }
 
+    const uint32_t *W = twi + (size_t)l * N;
+    const uint32_t *Wsh = twish + (size_t)l * N;
+    PassTw<LOGN, LOGR, T> ptw;
+    inv_tw_load<LOGN, LOGR, T, 0>(ptw, tid, W, Wsh);
     // coalesced load into LDS
 #pragma unroll
     for (int i = 0; i < (1 << LOGR); ++i) {
@@ -257,7 +379,7 @@ k_ntt_inv(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, RowMap m
     }
     __syncthreads();
     uint32_t v[1 << LOGR];
-    inv_pass<LOGN, LOGR, 0>(v, lds, tid, twi + (size_t)l * N, twish + (size_t)l * N, q, q2);
+    inv_pass<LOGN, LOGR, T, 0>(v, ptw, lds, tid, W, Wsh, q, q2);
 
 #pragma unroll
     for (int i = 0; i < (1 << LOGR); ++i) {
@@ -337,7 +459,10 @@ hipError_t inv_launch(const uint32_t *src, uint32_t *dst, const RowMap &map, uin
 // inverse table), then writes the span of residue classes its channels own:
 // out_g[s m + c] for c in [c_lo, c_lo + RW s / g_o), every m < M.
 template <int LOGM, int LOGR>
-__global__ void __launch_bounds__(1024)
+constexpr int tail_tpw() { return (1 << (LOGM - LOGR)) < 256 ? 256 : (1 << (LOGM - LOGR)); }
+
+template <int LOGM, int LOGR>
+__global__ void __launch_bounds__((tail_tpw<LOGM, LOGR>()))
 k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const uint32_t *__restrict__ sh_next,
             uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, uint32_t RW,
             const uint32_t *__restrict__ twi, const uint32_t *__restrict__ twish, LimbConsts lc) {
@@ -363,6 +488,10 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
     const bool active = row < RW;
     const uint32_t n = g * g_o + np0 + row;
     const bool exists = active && n < c_o;
+    const uint32_t *W = twi + (size_t)l * N;
+    const uint32_t *Wsh = twish + (size_t)l * N;
+    PassTw<LOGM, LOGR, tail_tpw<LOGM, LOGR>()> ptw;
+    inv_tw_load<LOGM, LOGR, tail_tpw<LOGM, LOGR>(), 0>(ptw, t, W, Wsh);
     if (active) {
         const uint32_t *src = h + ((size_t)(b * c_o + (exists ? n : 0)) * L + l) * M;
 #pragma unroll
@@ -373,7 +502,7 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
     }
     __syncthreads();
     uint32_t v[1 << LOGR];
-    inv_pass<LOGM, LOGR, 0>(v, my, t, twi + (size_t)l * N, twish + (size_t)l * N, c.q, c.q2);
+    inv_pass<LOGM, LOGR, tail_tpw<LOGM, LOGR>(), 0>(v, ptw, my, t, W, Wsh, c.q, c.q2);
     __syncthreads();
     if (active) {
 #pragma unroll
@@ -387,6 +516,7 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
     uint32_t *o = out + ((size_t)(b * K_out + g) * L + l) * N;
     const uint32_t *sh = sh_next ? sh_next + (size_t)(b * K_out + g) * N : nullptr;
     const uint32_t total = (uint32_t)M << span_log;
+#pragma unroll 4
     for (uint32_t e = tid; e < total; e += blockDim.x) {
         const uint32_t m = e >> span_log;
         const uint32_t off = e & ((1u << span_log) - 1u);
@@ -405,7 +535,7 @@ hipError_t tail_launch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next
                        const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
     if constexpr (valid_variant(LOGM, LOGR)) {
         constexpr int T = 1 << (LOGM - LOGR);
-        constexpr int TPW = T < 256 ? 256 : T;
+        constexpr int TPW = tail_tpw<LOGM, LOGR>();
         uint32_t RW = TPW / T;
         if (RW > g_o) RW = g_o;
         const uint32_t grid = B * K_out * L * (g_o / RW);
@@ -415,6 +545,113 @@ hipError_t tail_launch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ fused MAC + residue-class tail
+// One workgroup per output row (b, g, n', l), l fastest.  It accumulates the
+// coefficient-wise products of its channel over all N slots and sums the s
+// slots of each block (as the class-form MAC does), keeps the M = N/s block
+// sums in LDS, inverts them there (the M-point Gentleman-Sande of k_tail_rows)
+// and writes its span of residue classes plus Delta sh'.  Against the MAC and
+// tail launches it saves one launch and the round trip of the block sums
+// through memory; the sh' words it adds are fetched at entry so that their
+// latency overlaps the MAC.
+constexpr int MT_THREADS = 1024;
+constexpr int MT_PF = 8;   // sh' words per thread fetched at entry
+
+template <int LOGM>
+constexpr int mt_logr() { return LOGM - 10 > 2 ? LOGM - 10 : 2; }
+
+template <int LOGM>
+__global__ void __launch_bounds__(MT_THREADS)
+k_mac_tail(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ out,
+           const uint32_t *__restrict__ sh_next, uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t g_o,
+           uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, const uint32_t *__restrict__ twi,
+           const uint32_t *__restrict__ twish, LimbConsts lc) {
+    constexpr int LOGR = mt_logr<LOGM>();
+    constexpr int M = 1 << LOGM;
+    constexpr int T = 1 << (LOGM - LOGR);
+    __shared__ uint32_t lds[M + (M >> 5)];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tpb = blockDim.x;             // N/4 or MT_THREADS: every thread has the same chunk count
+    uint32_t w = blockIdx.x;
+    const uint32_t l = w % L;
+    w /= L;
+    const uint32_t np = w % g_o;
+    w /= g_o;
+    const uint32_t g = w % K_out;
+    const uint32_t b = w / K_out;
+    const uint32_t n = g * g_o + np;
+    const bool exists = n < c_o;                 // uniform over the workgroup
+    const LimbConst c = lc.l[l];
+    const uint32_t N = 1u << logN;
+    const uint32_t s = 1u << s_log;
+    // this channel's output span: classes [c_lo, c_lo + cw) of every block, cw = s / g_o
+    const uint32_t cw_log = s_log - (31u - __clz(g_o));
+    const uint32_t cw_mask = (1u << cw_log) - 1u;
+    const uint32_t c_lo = np << cw_log;
+    const uint32_t total = (uint32_t)M << cw_log;
+    uint32_t *o = out + ((size_t)(b * K_out + g) * L + l) * N;
+    const uint32_t *sh = sh_next ? sh_next + (size_t)(b * K_out + g) * N : nullptr;
+    uint32_t shv[MT_PF];
+#pragma unroll
+    for (int i = 0; i < MT_PF; ++i) {
+        const uint32_t e = tid + i * tpb;
+        shv[i] = (sh && e < total) ? sh[((e >> cw_log) << s_log) + c_lo + (e & cw_mask)] : 0u;
+    }
+    if (exists) {
+        const uint32_t *W = twi + (size_t)l * N;
+        const uint32_t *Wsh = twish + (size_t)l * N;
+        const bool act = tid < (uint32_t)T;
+        PassTw<LOGM, LOGR, MT_THREADS> ptw;
+        inv_tw_load<LOGM, LOGR, MT_THREADS, 0>(ptw, act ? tid : 0u, W, Wsh);
+        const uint32_t *x = X + ((size_t)b * Jtot * L + l) * N;
+        const uint32_t *op = Op + (size_t)(n * L + l) * Jtot * N;
+        for (uint32_t k4 = tid * 4u; k4 < N; k4 += tpb * 4u) {
+            uint32_t r[4];
+            mac4(x + k4, (size_t)L * N, op + k4, N, Juse, c, r);
+            if (s == 1) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) lds[lpad(k4 + i)] = r[i];
+            } else if (s == 2) {
+                lds[lpad(k4 >> 1)] = addmod(r[0], r[1], c.q);
+                lds[lpad((k4 >> 1) + 1)] = addmod(r[2], r[3], c.q);
+            } else {
+                // the s slots of a block are held by s/4 consecutive lanes
+                uint32_t v = r[0] + r[1] + r[2] + r[3];   // [0, 4q)
+                v = csub(csub(v, c.q2), c.q);
+                const uint32_t lanes = s >> 2;
+                for (uint32_t m = 1; m < lanes; m <<= 1) v = addmod(v, (uint32_t)__shfl_xor((int)v, (int)m), c.q);
+                if ((tid & (lanes - 1)) == 0) lds[lpad(k4 >> s_log)] = v;
+            }
+        }
+        __syncthreads();
+        uint32_t v[1 << LOGR];
+        inv_pass<LOGM, LOGR, MT_THREADS, 0>(v, ptw, lds, act ? tid : 0u, W, Wsh, c.q, c.q2, act);
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < (1 << LOGR); ++i) lds[lpad(inv_final_idx<LOGM, LOGR>(tid, i))] = csub(v[i], c.q);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < MT_PF; ++i) {
+        const uint32_t e = tid + i * tpb;
+        if (e < total) {
+            const uint32_t m = e >> cw_log, off = e & cw_mask;
+            uint32_t val = (exists && off == 0) ? lds[lpad(m)] : 0u;
+            if (sh) val = csub(val + mul_delta_msg(shv[i], c), c.q);
+            o[(m << s_log) + c_lo + off] = val;
+        }
+    }
+    for (uint32_t e = tid + MT_PF * tpb; e < total; e += tpb) {
+        const uint32_t m = e >> cw_log, off = e & cw_mask;
+        const uint32_t k = (m << s_log) + c_lo + off;
+        uint32_t val = (exists && off == 0) ? lds[lpad(m)] : 0u;
+        if (sh) val = csub(val + mul_delta_msg(sh[k], c), c.q);
+        o[k] = val;
     }
 }
 
@@ -508,4 +745,39 @@ hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh
         default: return hipErrorInvalidValue;
     }
 #undef HE_TAIL
+}
+
+hipError_t launch_mac_tail(const uint32_t *X, const uint32_t *Op, uint32_t *out, const uint32_t *sh_next, uint32_t B,
+                           uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L,
+                           uint32_t N, uint32_t s, const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
+                           hipStream_t st, const LaunchEv *ev) {
+    if (B == 0) return hipSuccess;
+    uint32_t logN = 0, s_log = 0;
+    while ((1u << logN) < N) ++logN;
+    while ((1u << s_log) < s) ++s_log;
+    const int logm = (int)(logN - s_log);
+    // s/4 lanes per block within one wave; every thread owns the same number of 4-slot chunks
+    if (s > 256 || logm < 4 || logm > 14 || N < 256 || g_o == 0 || g_o > s || Juse == 0) return hipErrorInvalidValue;
+    const uint32_t tpb = N / 4 < (uint32_t)MT_THREADS ? N / 4 : (uint32_t)MT_THREADS;
+    const uint32_t grid = B * K_out * g_o * L;
+#define HE_MT(LM)                                                                                                    \
+    case LM:                                                                                                         \
+        HE_LAUNCH(ev, k_mac_tail<LM>, dim3(grid), dim3(tpb), 0, st, X, Op, out, sh_next, Jtot, Juse, c_o, g_o, K_out, \
+                  L, logN, s_log, twi, twish, lc);                                                                   \
+        return hipGetLastError();
+    switch (logm) {
+        HE_MT(4)
+        HE_MT(5)
+        HE_MT(6)
+        HE_MT(7)
+        HE_MT(8)
+        HE_MT(9)
+        HE_MT(10)
+        HE_MT(11)
+        HE_MT(12)
+        HE_MT(13)
+        HE_MT(14)
+        default: return hipErrorInvalidValue;
+    }
+#undef HE_MT
 }

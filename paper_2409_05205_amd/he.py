@@ -35,7 +35,7 @@ EXPORTED = [
     "he_pack_operands", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
 ]
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
-HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT = 1, 2, 4, 8
+HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL = 1, 2, 4, 8, 16
 
 
 class HEError(RuntimeError):
