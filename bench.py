@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # Shoup Cooley-Tukey butterflies per second of the whole chip (256 CUs, 2.4 GHz): 7.3 per CU-clock,
 # measured at full occupancy for this instruction mix (mul_hi + 2 mul_lo + 6 add/compare).
 BFLY_PEAK_G = 4470.0
+# 32x32->64-bit multiply-adds (v_mad_u64_u32) per second of the whole chip, measured the same way:
+# the issue-rate ceiling of the MAC's inner product.
+MAD64_PEAK_G = 22400.0
 # HBM traffic per launch from the FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a 256 MiB
 # copy), valid while the kernel source is the one that was measured.
 PMC_TRAFFIC = {
@@ -169,6 +172,16 @@ class Stack:
             tot += B * ly.info.K_in * L * (2 if sh is not None else 1) * per_row
         return tot
 
+    def tail_butterflies(self):
+        """Inverse-transform butterflies of one pass: the (N/s)-point residue-class inverse of
+        every real output channel (conv), the N-point inverse of every row block (FC)."""
+        L, N = self.ctx.L, self.ctx.N
+        tot = 0
+        for (ly, B, c0, sh, shn), rows in zip(self.steps, self.rows):
+            M = N // ly.info.s if ly.kind == 0 and ly.info.flags == 0 else N
+            tot += B * rows * L * (M // 2) * (M.bit_length() - 1)
+        return tot
+
     def modmuls(self):
         """Coefficient-wise modular multiplications of the MAC in one pass."""
         tot = 0
@@ -196,6 +209,41 @@ def percentile(xs, p):
         return None
     k = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
     return xs[k]
+
+
+def batched_rooflines(he, ctx, st, stream, sync, passes=2):
+    """Per-kind kernel time of eager passes over a batched stack (HIP events on the launch
+    stream), against the integer roofs: forward and inverse butterflies against the measured
+    butterfly rate, MAC products against the 64-bit multiply-add rate."""
+    import torch
+    kinds = [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL), ("intt", he.HE_K_INTT),
+             ("mac_tail", he.HE_K_MAC_TAIL)]
+    ctx.profile_reset()
+    ctx.profile_enable(sum(k for _, k in kinds))
+    with torch.cuda.stream(stream):
+        for _ in range(passes):
+            st.seq.run(stream)
+    sync()
+    ms = {}
+    for name, kind in kinds:
+        n, t = ctx.profile_read(kind)
+        ms[name] = t / passes
+    ctx.profile_enable(0)
+    ctx.profile_reset()
+    out = {}
+    fwd_rate = st.butterflies_fwd() / (ms["ntt_fwd"] / 1e3) / 1e9 if ms["ntt_fwd"] else None
+    out["ntt_fwd"] = {"ms_per_batch": round(ms["ntt_fwd"], 3), "bound": "alu", "achieved": round(fwd_rate, 1),
+                      "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(fwd_rate / BFLY_PEAK_G, 4)}
+    mac_ms = ms["mac"] + ms["mac_tail"]
+    mac_rate = st.modmuls() / (mac_ms / 1e3) / 1e9
+    out["mac"] = {"ms_per_batch": round(mac_ms, 3), "bound": "alu", "achieved": round(mac_rate, 1),
+                  "peak": MAD64_PEAK_G, "unit": "Gmodmul/s", "frac": round(mac_rate / MAD64_PEAK_G, 4)}
+    inv_ms = ms["tail"] + ms["intt"]
+    if inv_ms:
+        inv_rate = st.tail_butterflies() / (inv_ms / 1e3) / 1e9
+        out["inverse"] = {"ms_per_batch": round(inv_ms, 3), "bound": "alu", "achieved": round(inv_rate, 1),
+                          "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(inv_rate / BFLY_PEAK_G, 4)}
+    return out
 
 
 # ------------------------------------------------------------------ CPU baseline
@@ -231,6 +279,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-widths", default="1,2,4", help="plain-20 widths of the batched form")
+    ap.add_argument("--batched-mac", type=int, default=None,
+                    help="pin the MAC variant of the batched form (HE_TUNE_MAC value) instead of tuning it")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=6000)
     ap.add_argument("--served-warmup", type=int, default=500)
@@ -383,10 +434,13 @@ def main():
         bres = {}
         tot_layers = 0
         tot_time = 0.0
-        for width, N, L in [(1, 8192, 4), (2, 8192, 4), (4, 16384, 6)]:
+        widths = [int(w) for w in args.batched_widths.split(",")]
+        for width, N, L in [(w, 8192 if w < 4 else 16384, 4 if w < 4 else 6) for w in widths]:
             log(f"setup: batched x{width} N={N} L={L}")
             bctx = ctx if N == 8192 else he.Context(N, L, wl.T_PLAIN)
             bst = Stack(he, bctx, wl.CONFIG_BATCHED, width, [10, 100], [32, 32], N, L)
+            if args.batched_mac is not None:
+                bctx.tune_force(he.HE_TUNE_MAC, args.batched_mac)
             if not args.no_tune:
                 bst.autotune()
             sync()
@@ -400,10 +454,13 @@ def main():
             bres[f"x{width}"] = {"layers_per_s": round(il * args.batched_steps / T, 1),
                                  "ms_per_batch": round(T / args.batched_steps * 1e3, 3),
                                  "image_layers_per_batch": il,
-                                 "limb_poly_macs_per_s": round(bst.modmuls() / N * args.batched_steps / T, 1)}
+                                 "limb_poly_macs_per_s": round(bst.modmuls() / N * args.batched_steps / T, 1),
+                                 "kernel_rooflines": batched_rooflines(he, bctx, bst, stream, sync)}
             log(f"batched x{width}: {json.dumps(bres[f'x{width}'])}")
             tot_layers += il * args.batched_steps
             tot_time += T
+            if args.batched_mac is not None:
+                bctx.tune_force(he.HE_TUNE_MAC, -1)
             del bseq, bst
             torch.cuda.empty_cache()
         bres["all_widths_layers_per_s"] = round(tot_layers / tot_time, 1)

@@ -291,9 +291,10 @@ void he_server_free(he_server *srv);
  * register radix log2 r in 2..5 (each thread keeps 2^r words and runs r stages
  * per LDS pass; 0 = automatic), HE_TUNE_MAC takes 0 (streaming per-image MAC),
  * 1 (register-blocked batched MAC), 2 (residue-class conv layers: MAC, inverse
- * and extraction fused, one workgroup per output row) or -1 (automatic: 2 at
- * B = 1, 1 at B >= 4); a value the layer's shape does not allow falls back to
- * 0.  Every value yields the same output words.  he_tune_force pins a knob for the whole context (tests
+ * and extraction fused, one workgroup per output row), 3 (residue-class conv
+ * layers, B >= 2: LDS-staged batched MAC over image x channel tiles) or -1
+ * (automatic: 2 at B = 1, 1 at B >= 4); a value the layer's shape does not
+ * allow falls back to 0.  Every value yields the same output words.  he_tune_force pins a knob for the whole context (tests
  * sweep all values with it).  he_autotune_layer tunes the knobs of one layer at
  * batch B one after another: each candidate is timed as a whole layer call on
  * scratch buffers (median of 5, caches evicted before each), and the fastest is

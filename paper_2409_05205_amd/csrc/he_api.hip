@@ -205,9 +205,15 @@ bool mac_fused_ok(const he_ctx *ctx, const he_layer *ly) {
     return in.kind == HE_LAYER_CONV && in.flags == HE_PACK_CLASS_INTT && logm >= 4 && in.s <= 256 && in.N >= 256;
 }
 
+bool mac_lds_ok(const he_layer *ly, uint32_t B) {
+    const he_layer_info &in = ly->info;
+    return B >= 2 && in.kind == HE_LAYER_CONV && in.flags == HE_PACK_CLASS_INTT && in.s >= 2 && in.N >= 256;
+}
+
 int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
     const int mk = knob(ctx, HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B);
     const bool tiled_ok = mac_tiled_ok(ly, B), fused_ok = mac_fused_ok(ctx, ly);
+    if (mk == 3) return mac_lds_ok(ly, B) ? 3 : 0;
     if (mk == 2) return fused_ok ? 2 : 0;
     if (mk == 1) return tiled_ok ? 1 : 0;
     if (mk == 0) return 0;
@@ -469,6 +475,7 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         std::vector<int> macs{0};
         if (mac_tiled_ok(ly, B)) macs.push_back(1);
         if (mac_fused_ok(ctx, ly)) macs.push_back(2);
+        if (mac_lds_ok(ly, B)) macs.push_back(3);
         if (rc == HE_OK && macs.size() > 1) rc = pick(HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B, macs, true);
         const uint32_t logm = logN - log2u(in.s);
         const uint32_t rows = B * in.K_out * in.g_o * L;
@@ -932,7 +939,9 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
     {
         const bool tiled = mk == 1;
         ProfScope ps(ctx, HE_K_MAC);
-        if (tiled)
+        if (mk == 3)
+            e = launch_mac_lds(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, ctx->lc, st, ps.ev());
+        else if (tiled)
             e = launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, cls, ctx->lc, st, ps.ev());
         else if (cls)
             e = launch_mac_class(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, ctx->lc, st, ps.ev());

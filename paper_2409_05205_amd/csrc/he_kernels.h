@@ -100,6 +100,21 @@ hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh
                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
                             const LaunchEv *ev = nullptr, int logr = 0);
 
+// LDS-staged batched MAC, residue-class form (s >= 2): same output as launch_mac_class.
+struct MacLdsGeom {
+    uint32_t TBq, TNq;        // thread sub-tile grid: TB = 4 TBq images x TN = 4 TNq channels
+    uint32_t GS, R;           // slots per thread span and per staged input row
+    uint32_t JS;              // input rows per stage
+    uint32_t cpb, gpb;        // stages per block and row (1 when a stage holds whole blocks); groups per block
+    uint32_t ranges;          // slot ranges per limb
+    uint32_t rpw;             // consecutive slot ranges per workgroup (set at launch)
+    uint32_t tiles_b, tiles_n;
+};
+bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGeom *gm, size_t *lds_bytes);
+hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
+                          uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
+                          hipStream_t st, const LaunchEv *ev = nullptr);
+
 // Fused class-form MAC + residue-class tail: one workgroup per output row
 // (b, g, n', l); same output as launch_mac_class followed by launch_tail_rows.
 // Requires s <= 256, 16 <= N/s <= 16384, N >= 256.

@@ -103,8 +103,10 @@ k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uin
     const uint32_t l = S / chunks;
     const uint32_t k2 = (S % chunks) * TB_SLOTS + threadIdx.x * 2u;
     const bool live = k2 < N;
-    const uint32_t b0 = (t / tiles_n) * TB_IB;
-    const uint32_t n0 = (t % tiles_n) * TB_NB;
+    // image tiles fastest: the workgroups resident on an XCD at one time share a few
+    // operand tiles (each read from HBM once) and the slice's inputs, which fit its L2
+    const uint32_t b0 = (t % tiles_b) * TB_IB;
+    const uint32_t n0 = (t / tiles_b) * TB_NB;
     const LimbConst c = lc.l[l];
     uint64_t acc[TB_IB][TB_NB][NS];
 #pragma unroll
@@ -176,6 +178,198 @@ k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uin
                 for (uint32_t m = 1; m < lanes; m <<= 1) v = addmod(v, (uint32_t)__shfl_xor((int)v, (int)m), c.q);
                 if (mine && (threadIdx.x & (lanes - 1)) == 0) dst[k2 >> s_log] = v;
             }
+        }
+}
+
+// ------------------------------------------------------------------ batched MAC, LDS-staged
+// Residue-class form only.  Per NTT slot the MAC is a small product of an
+// (images x J) and a (J x channels) matrix, summed over the s slots of each
+// block.  A workgroup takes a tile of TB images x TN channels of one limb and a
+// range of slots; per stage (one input row J, R slots) it stages the TB + TN
+// rows of R words in LDS (double-buffered, loads of the next stage in flight
+// during the products), and each thread accumulates a 4 x 4 sub-tile (images
+// bi + TBq u, channels ni + TNq v) over GS consecutive slots of one block, so a
+// staged word feeds 4 products from LDS and a global word TB or TN.  Threads are
+// split into G groups by slot span; when a block spans several groups their
+// sums are added through LDS at the end.  The 64-bit sums are kept below 2^64 by
+// replacing hi 2^32 + lo with hi (2^32 mod q) + lo (one multiply-add) every 10
+// products, and reduced mod q once at the end.
+constexpr int ML_THREADS = 256;
+constexpr int ML_UNITS = 4;          // 16-byte staging loads per thread and stage (R <= 32)
+constexpr int ML_RED_STRIDE = 17;    // words per thread in the cross-group sum (16 + pad)
+
+template <int GS>
+__global__ void __launch_bounds__(ML_THREADS)
+k_mac_lds(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ h, uint32_t B,
+          uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s_log, MacLdsGeom gm,
+          LimbConsts lc) {
+    extern __shared__ uint32_t lds[];
+    // rows padded by two words: 8-byte aligned pairs, and 16 rows of a wave on distinct banks
+    const uint32_t TBq = gm.TBq, TNq = gm.TNq, TB = 4 * TBq, TN = 4 * TNq, RP = gm.R + 2, R4 = gm.R >> 2;
+    const uint32_t JS = gm.JS, row_words = (TB + TN) * RP;   // one input row J of a stage
+    const uint32_t buf_words = JS * row_words;
+    uint32_t w = blockIdx.x;
+    const uint32_t tb = w % gm.tiles_b;
+    w /= gm.tiles_b;
+    const uint32_t tn = w % gm.tiles_n;
+    w /= gm.tiles_n;
+    const uint32_t rgroups = gm.ranges / gm.rpw;
+    const uint32_t range0 = (w % rgroups) * gm.rpw;   // this workgroup's first slot range
+    const uint32_t l = w / rgroups;
+    const uint32_t b0 = tb * TB, n0 = tn * TN;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sub = tid % (TBq * TNq);
+    const uint32_t g = tid / (TBq * TNq);
+    const uint32_t bi = sub / TNq, ni = sub % TNq;
+    const LimbConst c = lc.l[l];
+    const uint32_t range_slots = gm.R * gm.cpb;
+    const uint32_t jblocks = (Juse + JS - 1) / JS;
+    const uint32_t spr = jblocks * gm.cpb;             // stages per slot range
+    const uint32_t stages = gm.rpw * spr;
+    const uint32_t units_j = (TB + TN) * R4;   // per input row
+    const uint32_t units = JS * units_j;
+
+    // staging unit u of stage st: input row J = JS (st / cpb) + u / units_j, then within that row
+    // row r = (u % units_j) / R4 (x rows first, then operand rows), 4 words at column 4 (u % R4)
+    auto load_stage = [&](uint32_t st, uint4 (&pre)[ML_UNITS]) {
+        const uint32_t loc = st % spr;
+        const uint32_t J0 = (loc / gm.cpb) * JS;
+        const uint32_t k_st = (range0 + st / spr) * range_slots + (loc % gm.cpb) * gm.R;
+#pragma unroll
+        for (int i = 0; i < ML_UNITS; ++i) {
+            const uint32_t u = tid + i * ML_THREADS;
+            const uint32_t J = J0 + u / units_j;
+            if (u < units && J < Juse) {
+                const uint32_t rem = u % units_j;
+                const uint32_t row = rem / R4, k = k_st + (rem % R4) * 4;
+                const uint32_t *src;
+                if (row < TB) {
+                    const uint32_t b = min(b0 + row, B - 1);
+                    src = X + (((size_t)b * Jtot + J) * L + l) * N + k;
+                } else {
+                    const uint32_t n = min(n0 + row - TB, c_o - 1);
+                    src = Op + (((size_t)n * L + l) * Jtot + J) * N + k;
+                }
+                pre[i] = *reinterpret_cast<const uint4 *>(src);
+            }
+        }
+    };
+    auto store_stage = [&](uint32_t st, uint32_t buf, const uint4 (&pre)[ML_UNITS]) {
+        uint32_t *dst = lds + buf * buf_words;
+        const uint32_t J0 = ((st % spr) / gm.cpb) * JS;
+#pragma unroll
+        for (int i = 0; i < ML_UNITS; ++i) {
+            const uint32_t u = tid + i * ML_THREADS;
+            if (u < units && J0 + u / units_j < Juse) {
+                const uint32_t rem = u % units_j;
+                uint2 *d = reinterpret_cast<uint2 *>(dst + (u / units_j) * row_words + (rem / R4) * RP +
+                                                     (rem % R4) * 4);
+                d[0] = make_uint2(pre[i].x, pre[i].y);
+                d[1] = make_uint2(pre[i].z, pre[i].w);
+            }
+        }
+    };
+
+    uint64_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    uint32_t pc = 0;   // products in acc since the last fold (uniform)
+    uint4 pre[ML_UNITS];
+    load_stage(0, pre);
+    store_stage(0, 0, pre);
+    __syncthreads();
+    const uint32_t off = g * GS;   // even: 8-byte aligned pairs
+    for (uint32_t st = 0; st < stages; ++st) {
+        const uint32_t buf = st & 1u;
+        if (st + 1 < stages) load_stage(st + 1, pre);
+        const uint32_t jn = min(JS, Juse - ((st % spr) / gm.cpb) * JS);   // input rows in this stage
+        for (uint32_t jj = 0; jj < jn; ++jj) {
+        const uint32_t *xs = lds + buf * buf_words + jj * row_words + off;
+        const uint32_t *os = xs + TB * RP;
+        const uint2 *xr[4], *orow[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xr[u] = reinterpret_cast<const uint2 *>(xs + (bi + TBq * u) * RP);
+            orow[u] = reinterpret_cast<const uint2 *>(os + (ni + TNq * u) * RP);
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < GS / 2; ++k2) {   // two slots per 8-byte read
+            uint2 xv[4], ov[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xv[u] = xr[u][k2];
+                ov[u] = orow[u][k2];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j] += (uint64_t)xv[i].x * ov[j].x;
+                    acc[i][j] += (uint64_t)xv[i].y * ov[j].y;
+                }
+            pc += 2;
+            if (pc >= 10) {
+                // hi 2^32 + lo == hi (2^32 mod q) + lo: below 2^62 + 2^32, and ten more
+                // products keep the sum below 2^64
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = (uint64_t)(uint32_t)(acc[i][j] >> 32) * c.r32 + (acc[i][j] & 0xffffffffull);
+                pc = 0;
+            }
+        }
+        }
+        if (st + 1 < stages) store_stage(st + 1, buf ^ 1u, pre);
+        __syncthreads();
+        if (gm.gpb == 1 && st % spr == spr - 1) {
+            // a slot range is complete and no other group shares its blocks: write, start the next
+            const uint32_t M = N >> s_log;
+            const uint32_t m = ((range0 + st / spr) * range_slots + off) >> s_log;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t b = b0 + bi + TBq * i, n = n0 + ni + TNq * j;
+                    if (b < B && n < c_o) h[((size_t)(b * c_o + n) * L + l) * M + m] = reduce64(acc[i][j], c);
+                    acc[i][j] = 0;
+                }
+            pc = 0;
+        }
+    }
+    if (gm.gpb == 1) return;
+    // one slot range per workgroup (rpw = 1)
+    const uint32_t base = range0 * range_slots;
+    uint32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[i * 4 + j] = reduce64(acc[i][j], c);
+    {
+        // the gpb groups that share a block are consecutive; the first adds the others' sums
+        uint32_t *red = lds;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) red[tid * ML_RED_STRIDE + u] = v[u];
+        __syncthreads();
+        if (g % gm.gpb == 0) {
+            for (uint32_t p = 1; p < gm.gpb; ++p) {
+                const uint32_t *o = red + (tid + p * TBq * TNq) * ML_RED_STRIDE;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) v[u] = addmod(v[u], o[u], c.q);
+            }
+        }
+    }
+    if (g % gm.gpb != 0) return;
+    const uint32_t M = N >> s_log;
+    const uint32_t m = (base + off) >> s_log;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t b = b0 + bi + TBq * i, n = n0 + ni + TNq * j;
+            if (b < B && n < c_o) h[((size_t)(b * c_o + n) * L + l) * M + m] = v[i * 4 + j];
         }
 }
 
@@ -376,5 +570,79 @@ hipError_t launch_mac_tiled(const uint32_t *X, const uint32_t *Op, uint32_t *out
     else
         HE_LAUNCH(ev, k_mac_tiled<false>, dim3(grid), dim3(TB_THREADS), 0, st, X, Op, out, B, Jtot, Juse, c_o, L, N,
                   s_log, n_super, tiles_b, tiles_n, lc);
+    return hipGetLastError();
+}
+
+bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGeom *gm, size_t *lds_bytes) {
+    if (B == 0 || c_o == 0 || s < 2 || s > N || N < 256) return false;
+    auto pow2_at_least = [](uint32_t x) {
+        uint32_t p = 1;
+        while (p < x) p <<= 1;
+        return p;
+    };
+    uint32_t TBq = pow2_at_least((B + 3) / 4), TNq = pow2_at_least((c_o + 3) / 4);
+    if (TBq > 16) TBq = 16;
+    if (TNq > 16) TNq = 16;
+    const uint32_t GS = s < 16 ? s : 16;
+    // R staged slots per input row, at most 32 (ML_UNITS loads per thread), at least 4 (16-byte
+    // loads); 32 / R input rows per stage
+    while ((ML_THREADS / (TBq * TNq)) * GS > 32) {
+        if (TBq <= TNq && TBq < 16) TBq <<= 1;
+        else if (TNq < 16) TNq <<= 1;
+        else break;   // 16 x 16: one group, R = GS <= 16
+    }
+    while ((ML_THREADS / (TBq * TNq)) * GS < 4) {
+        if (TNq >= TBq && TNq > 1) TNq >>= 1;
+        else TBq >>= 1;
+    }
+    const uint32_t G = ML_THREADS / (TBq * TNq);
+    const uint32_t R = G * GS;
+    const uint32_t spans = s / GS;            // thread spans per block
+    gm->TBq = TBq;
+    gm->TNq = TNq;
+    gm->GS = GS;
+    gm->R = R;
+    if (spans <= G) {
+        gm->cpb = 1;
+        gm->gpb = spans;
+    } else {
+        gm->cpb = spans / G;
+        gm->gpb = G;
+    }
+    gm->ranges = N / (R * gm->cpb);
+    gm->rpw = 1;
+    gm->JS = 32 / R;                          // input rows per stage: 32 row-slots staged per stage
+    gm->tiles_b = (B + 4 * TBq - 1) / (4 * TBq);
+    gm->tiles_n = (c_o + 4 * TNq - 1) / (4 * TNq);
+    const size_t stage = (size_t)2 * gm->JS * 4 * (TBq + TNq) * (R + 2);
+    const size_t red = (size_t)ML_THREADS * ML_RED_STRIDE;
+    *lds_bytes = (stage > red ? stage : red) * sizeof(uint32_t);
+    return true;
+}
+
+hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
+                          uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
+                          hipStream_t st, const LaunchEv *ev) {
+    if (B == 0) return hipSuccess;
+    MacLdsGeom gm;
+    size_t lds = 0;
+    if (Juse == 0 || !mac_lds_geometry(B, c_o, N, s, &gm, &lds)) return hipErrorInvalidValue;
+    uint32_t s_log = 0;
+    while ((1u << s_log) < s) ++s_log;
+    // several consecutive slot ranges per workgroup (when no block is shared between thread
+    // groups) until it runs >= 16 stages, keeping >= 2048 workgroups
+    const uint32_t spr = ((Juse + gm.JS - 1) / gm.JS) * gm.cpb;
+    gm.rpw = 1;
+    while (gm.gpb == 1 && gm.rpw * spr < 16 && gm.ranges % (2 * gm.rpw) == 0 &&
+           L * (gm.ranges / (2 * gm.rpw)) * gm.tiles_b * gm.tiles_n >= 2048)
+        gm.rpw *= 2;
+    const uint32_t grid = L * (gm.ranges / gm.rpw) * gm.tiles_b * gm.tiles_n;
+    switch (gm.GS) {
+        case 2: HE_LAUNCH(ev, k_mac_lds<2>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
+        case 4: HE_LAUNCH(ev, k_mac_lds<4>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
+        case 8: HE_LAUNCH(ev, k_mac_lds<8>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
+        case 16: HE_LAUNCH(ev, k_mac_lds<16>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }

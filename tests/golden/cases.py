@@ -86,3 +86,24 @@ WIDE_SAMPLES = [
     ("plain20_x2_c100", wl.CONFIG_BATCHED, 2, 100, 8192, 4, [19]),
     ("plain20_x4", wl.CONFIG_STRESS, 4, 100, 16384, 6, [0, 7, 13, 14, 19]),
 ]
+
+# Batched full-size layers: (name, config, width, classes, N, L, layer, batch, sampled images).
+# The GPU runs the whole batch; the oracle digests of the sampled images are stored.
+BATCHED_SAMPLES = [
+    ("batched_x2_l1", wl.CONFIG_BATCHED, 2, 10, 8192, 4, 1, 64, [3, 62]),
+    ("batched_x4_l1", wl.CONFIG_BATCHED, 4, 100, 16384, 6, 1, 64, [0, 45]),
+]
+
+
+def batched_layer_inputs(cfg, width, classes, k, B, N, primes):
+    """Server inputs of conv layer k of a plain-20 width variant for a batch of B images, drawn as
+    the batched benchmark draws them: c0 uniform per limb, shares uniform in [0, t)."""
+    shp = wl.plain20(width, classes)[k]
+    g = packing.conv_geometry(N, shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
+    L = len(primes)
+    F = wl.layer_weights(cfg, width, k, shp)
+    rho = wl.mask_polys(cfg, width, k, g.K_in * shp.c_o, N).reshape(g.K_in, shp.c_o, N)
+    c0 = wl.ciphertext_polys(cfg, 0, width, k, B * g.K_in, primes, N).reshape(B, g.K_in, L, N)
+    sh = wl.share_polys(cfg, 0, width, k, B * g.K_in, N).reshape(B, g.K_in, N)
+    shn = wl.share_polys(cfg, 0, width, k, B * g.K_out, N, "shnext").reshape(B, g.K_out, N)
+    return {"shape": shp, "geom": g, "F": F, "rho": rho, "c0": c0, "sh": sh, "sh_next": shn}

@@ -2,7 +2,8 @@
 
 For every full-size case in cases.py this script runs the oracle's server
 evaluation (Alg. 1 / Alg. 2, exact reading) on the seeded inputs and stores the
-SHA-256 of c0^r as little-endian u32 words.  For the x1 plain-20 stack and the
+SHA-256 of c0^r as little-endian u32 words (for the batched layers, of the
+sampled images of the batch).  For the x1 plain-20 stack and the
 single-conv workload it also runs the oracle client (masks p1/p2, client
 evaluation, decryption) and asserts that every decrypted output minus the fresh
 share equals the integer layer output mod t, i.e. that the closed loop of the
@@ -100,6 +101,20 @@ def main():
     out["cases"][name] = run_stack(name, cfg, width, classes, N, L, idx, decrypt=True)
     for name, cfg, width, classes, N, L, idx in cases.WIDE_SAMPLES:
         out["cases"][name] = run_stack(name, cfg, width, classes, N, L, idx, decrypt=False)
+    for name, cfg, width, classes, N, L, k, B, images in cases.BATCHED_SAMPLES:
+        ctx = bfv.make_ctx(N, L, wl.T_PLAIN)
+        inp = cases.batched_layer_inputs(cfg, width, classes, k, B, N, ctx.primes)
+        g = inp["geom"]
+        fh = packing.pack_conv_filters(inp["F"], g)
+        res = {"config": cfg, "width": width, "classes": classes, "N": N, "L": L, "layer": k, "batch": B,
+               "images": {}}
+        for b in images:
+            t0 = time.time()
+            o = bfv.server_conv(ctx, g, inp["c0"][b].astype(np.uint64), inp["rho"], fh, inp["sh"][b],
+                                inp["sh_next"][b])
+            res["images"][str(b)] = cases.digest(o)
+            print(f"{name} image {b} {time.time() - t0:.1f}s", flush=True)
+        out["cases"][name] = res
     with open(os.path.join(HERE, "server_digests.json"), "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
     print("wrote server_digests.json")

@@ -18,7 +18,7 @@ sys.path.insert(0, os.path.join(HERE, "golden"))
 import cases  # noqa: E402
 import workloads as wl  # noqa: E402
 from oracle import bfv  # noqa: E402
-from gpu_helpers import gpu_conv, gpu_fc  # noqa: E402
+from gpu_helpers import dev, gpu_conv, gpu_fc, host  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -96,3 +96,27 @@ def test_single_conv_digest(he):
     for flags in (0, 1):
         got = gpu_conv(ctx, inp["geom"], inp["F"], inp["rho"], inp["c0"], inp["sh"], inp["sh_next"], flags)
         assert cases.digest(got) == gold()["single_conv"]["layers"]["0"]["digest"]
+
+
+@pytest.mark.parametrize("case", cases.BATCHED_SAMPLES, ids=lambda c: c[0])
+def test_batched_layer_digest(he, case):
+    """A full batch of 64 images through one wide layer under every batched MAC variant (the
+    LDS-staged one walking several slot ranges per workgroup at this size); the sampled
+    images must match the oracle's digests."""
+    name, cfg, width, classes, N, L, k, B, images = case
+    ctx, octx = contexts(he, N, L)
+    inp = cases.batched_layer_inputs(cfg, width, classes, k, B, N, octx.primes)
+    g = inp["geom"]
+    want = gold()[name]["images"]
+    print(f"case {name} layer {k} B={B} s={g.s}", flush=True)
+    spec = he.ConvSpec(g.c_i, g.c_o, g.H, g.W, g.f, g.stride, g.pad)
+    layer = ctx.pack_conv(spec, inp["F"], inp["rho"])
+    c0, sh, shn = dev(inp["c0"]), dev(inp["sh"]), dev(inp["sh_next"])
+    try:
+        for mac in (3, 1, 0):
+            ctx.tune_force(he.HE_TUNE_MAC, mac)
+            got = host(ctx.conv_layer(layer, c0, sh, shn))
+            for b in images:
+                assert cases.digest(got[b]) == want[str(b)], f"mac={mac} image {b}"
+    finally:
+        ctx.tune_force(he.HE_TUNE_MAC, -1)
