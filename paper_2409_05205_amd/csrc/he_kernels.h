@@ -103,11 +103,9 @@ hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh
 // LDS-staged batched MAC, residue-class form (s >= 2): same output as launch_mac_class.
 struct MacLdsGeom {
     uint32_t TBq, TNq;        // thread sub-tile grid: TB = 4 TBq images x TN = 4 TNq channels
-    uint32_t GS, R;           // slots per thread span and per staged input row
-    uint32_t JS;              // input rows per stage
+    uint32_t GS, R;           // slots per thread span and per stage
     uint32_t cpb, gpb;        // stages per block and row (1 when a stage holds whole blocks); groups per block
     uint32_t ranges;          // slot ranges per limb
-    uint32_t rpw;             // consecutive slot ranges per workgroup (set at launch)
     uint32_t tiles_b, tiles_n;
 };
 bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGeom *gm, size_t *lds_bytes);

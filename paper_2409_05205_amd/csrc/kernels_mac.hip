@@ -206,42 +206,33 @@ k_mac_lds(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint3
     extern __shared__ uint32_t lds[];
     // rows padded by two words: 8-byte aligned pairs, and 16 rows of a wave on distinct banks
     const uint32_t TBq = gm.TBq, TNq = gm.TNq, TB = 4 * TBq, TN = 4 * TNq, RP = gm.R + 2, R4 = gm.R >> 2;
-    const uint32_t JS = gm.JS, row_words = (TB + TN) * RP;   // one input row J of a stage
-    const uint32_t buf_words = JS * row_words;
+    const uint32_t buf_words = (TB + TN) * RP;   // one stage: one input row J, R slots
     uint32_t w = blockIdx.x;
     const uint32_t tb = w % gm.tiles_b;
     w /= gm.tiles_b;
     const uint32_t tn = w % gm.tiles_n;
     w /= gm.tiles_n;
-    const uint32_t rgroups = gm.ranges / gm.rpw;
-    const uint32_t range0 = (w % rgroups) * gm.rpw;   // this workgroup's first slot range
-    const uint32_t l = w / rgroups;
+    const uint32_t range = w % gm.ranges;
+    const uint32_t l = w / gm.ranges;
     const uint32_t b0 = tb * TB, n0 = tn * TN;
     const uint32_t tid = threadIdx.x;
     const uint32_t sub = tid % (TBq * TNq);
     const uint32_t g = tid / (TBq * TNq);
     const uint32_t bi = sub / TNq, ni = sub % TNq;
     const LimbConst c = lc.l[l];
-    const uint32_t range_slots = gm.R * gm.cpb;
-    const uint32_t jblocks = (Juse + JS - 1) / JS;
-    const uint32_t spr = jblocks * gm.cpb;             // stages per slot range
-    const uint32_t stages = gm.rpw * spr;
-    const uint32_t units_j = (TB + TN) * R4;   // per input row
-    const uint32_t units = JS * units_j;
+    const uint32_t base = range * gm.R * gm.cpb;
+    const uint32_t stages = Juse * gm.cpb;
+    const uint32_t units = (TB + TN) * R4;
 
-    // staging unit u of stage st: input row J = JS (st / cpb) + u / units_j, then within that row
-    // row r = (u % units_j) / R4 (x rows first, then operand rows), 4 words at column 4 (u % R4)
+    // staging unit u of stage st: input row J = st / cpb, row u / R4 of the tile (x rows first,
+    // then operand rows), 4 words at column 4 (u % R4)
     auto load_stage = [&](uint32_t st, uint4 (&pre)[ML_UNITS]) {
-        const uint32_t loc = st % spr;
-        const uint32_t J0 = (loc / gm.cpb) * JS;
-        const uint32_t k_st = (range0 + st / spr) * range_slots + (loc % gm.cpb) * gm.R;
+        const uint32_t J = st / gm.cpb, k_st = base + (st % gm.cpb) * gm.R;
 #pragma unroll
         for (int i = 0; i < ML_UNITS; ++i) {
             const uint32_t u = tid + i * ML_THREADS;
-            const uint32_t J = J0 + u / units_j;
-            if (u < units && J < Juse) {
-                const uint32_t rem = u % units_j;
-                const uint32_t row = rem / R4, k = k_st + (rem % R4) * 4;
+            if (u < units) {
+                const uint32_t row = u / R4, k = k_st + (u % R4) * 4;
                 const uint32_t *src;
                 if (row < TB) {
                     const uint32_t b = min(b0 + row, B - 1);
@@ -254,16 +245,13 @@ k_mac_lds(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint3
             }
         }
     };
-    auto store_stage = [&](uint32_t st, uint32_t buf, const uint4 (&pre)[ML_UNITS]) {
+    auto store_stage = [&](uint32_t buf, const uint4 (&pre)[ML_UNITS]) {
         uint32_t *dst = lds + buf * buf_words;
-        const uint32_t J0 = ((st % spr) / gm.cpb) * JS;
 #pragma unroll
         for (int i = 0; i < ML_UNITS; ++i) {
             const uint32_t u = tid + i * ML_THREADS;
-            if (u < units && J0 + u / units_j < Juse) {
-                const uint32_t rem = u % units_j;
-                uint2 *d = reinterpret_cast<uint2 *>(dst + (u / units_j) * row_words + (rem / R4) * RP +
-                                                     (rem % R4) * 4);
+            if (u < units) {
+                uint2 *d = reinterpret_cast<uint2 *>(dst + (u / R4) * RP + (u % R4) * 4);
                 d[0] = make_uint2(pre[i].x, pre[i].y);
                 d[1] = make_uint2(pre[i].z, pre[i].w);
             }
@@ -278,15 +266,13 @@ k_mac_lds(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint3
     uint32_t pc = 0;   // products in acc since the last fold (uniform)
     uint4 pre[ML_UNITS];
     load_stage(0, pre);
-    store_stage(0, 0, pre);
+    store_stage(0, pre);
     __syncthreads();
     const uint32_t off = g * GS;   // even: 8-byte aligned pairs
     for (uint32_t st = 0; st < stages; ++st) {
         const uint32_t buf = st & 1u;
         if (st + 1 < stages) load_stage(st + 1, pre);
-        const uint32_t jn = min(JS, Juse - ((st % spr) / gm.cpb) * JS);   // input rows in this stage
-        for (uint32_t jj = 0; jj < jn; ++jj) {
-        const uint32_t *xs = lds + buf * buf_words + jj * row_words + off;
+        const uint32_t *xs = lds + buf * buf_words + off;
         const uint32_t *os = xs + TB * RP;
         const uint2 *xr[4], *orow[4];
 #pragma unroll
@@ -321,33 +307,15 @@ k_mac_lds(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint3
                 pc = 0;
             }
         }
-        }
-        if (st + 1 < stages) store_stage(st + 1, buf ^ 1u, pre);
+        if (st + 1 < stages) store_stage(buf ^ 1u, pre);
         __syncthreads();
-        if (gm.gpb == 1 && st % spr == spr - 1) {
-            // a slot range is complete and no other group shares its blocks: write, start the next
-            const uint32_t M = N >> s_log;
-            const uint32_t m = ((range0 + st / spr) * range_slots + off) >> s_log;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t b = b0 + bi + TBq * i, n = n0 + ni + TNq * j;
-                    if (b < B && n < c_o) h[((size_t)(b * c_o + n) * L + l) * M + m] = reduce64(acc[i][j], c);
-                    acc[i][j] = 0;
-                }
-            pc = 0;
-        }
     }
-    if (gm.gpb == 1) return;
-    // one slot range per workgroup (rpw = 1)
-    const uint32_t base = range0 * range_slots;
     uint32_t v[16];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) v[i * 4 + j] = reduce64(acc[i][j], c);
-    {
+    if (gm.gpb > 1) {
         // the gpb groups that share a block are consecutive; the first adds the others' sums
         uint32_t *red = lds;
 #pragma unroll
@@ -584,8 +552,7 @@ bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGe
     if (TBq > 16) TBq = 16;
     if (TNq > 16) TNq = 16;
     const uint32_t GS = s < 16 ? s : 16;
-    // R staged slots per input row, at most 32 (ML_UNITS loads per thread), at least 4 (16-byte
-    // loads); 32 / R input rows per stage
+    // R staged slots per stage, at most 32 (ML_UNITS loads per thread), at least 4 (16-byte loads)
     while ((ML_THREADS / (TBq * TNq)) * GS > 32) {
         if (TBq <= TNq && TBq < 16) TBq <<= 1;
         else if (TNq < 16) TNq <<= 1;
@@ -594,6 +561,12 @@ bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGe
     while ((ML_THREADS / (TBq * TNq)) * GS < 4) {
         if (TNq >= TBq && TNq > 1) TNq >>= 1;
         else TBq >>= 1;
+    }
+    // blocks shorter than 16 slots: stage 32 slots (rows of 128 contiguous bytes), trading
+    // image x channel reuse for full-line loads
+    while (GS < 16 && (ML_THREADS / (TBq * TNq)) * GS < 32 && TBq * TNq > 1) {
+        if (TBq >= TNq) TBq >>= 1;
+        else TNq >>= 1;
     }
     const uint32_t G = ML_THREADS / (TBq * TNq);
     const uint32_t R = G * GS;
@@ -610,11 +583,9 @@ bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGe
         gm->gpb = G;
     }
     gm->ranges = N / (R * gm->cpb);
-    gm->rpw = 1;
-    gm->JS = 32 / R;                          // input rows per stage: 32 row-slots staged per stage
     gm->tiles_b = (B + 4 * TBq - 1) / (4 * TBq);
     gm->tiles_n = (c_o + 4 * TNq - 1) / (4 * TNq);
-    const size_t stage = (size_t)2 * gm->JS * 4 * (TBq + TNq) * (R + 2);
+    const size_t stage = (size_t)2 * 4 * (TBq + TNq) * (R + 2);
     const size_t red = (size_t)ML_THREADS * ML_RED_STRIDE;
     *lds_bytes = (stage > red ? stage : red) * sizeof(uint32_t);
     return true;
@@ -629,14 +600,7 @@ hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, ui
     if (Juse == 0 || !mac_lds_geometry(B, c_o, N, s, &gm, &lds)) return hipErrorInvalidValue;
     uint32_t s_log = 0;
     while ((1u << s_log) < s) ++s_log;
-    // several consecutive slot ranges per workgroup (when no block is shared between thread
-    // groups) until it runs >= 16 stages, keeping >= 2048 workgroups
-    const uint32_t spr = ((Juse + gm.JS - 1) / gm.JS) * gm.cpb;
-    gm.rpw = 1;
-    while (gm.gpb == 1 && gm.rpw * spr < 16 && gm.ranges % (2 * gm.rpw) == 0 &&
-           L * (gm.ranges / (2 * gm.rpw)) * gm.tiles_b * gm.tiles_n >= 2048)
-        gm.rpw *= 2;
-    const uint32_t grid = L * (gm.ranges / gm.rpw) * gm.tiles_b * gm.tiles_n;
+    const uint32_t grid = L * gm.ranges * gm.tiles_b * gm.tiles_n;
     switch (gm.GS) {
         case 2: HE_LAUNCH(ev, k_mac_lds<2>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
         case 4: HE_LAUNCH(ev, k_mac_lds<4>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
