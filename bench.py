@@ -43,21 +43,27 @@ MAD64_PEAK_G = 22400.0
 # HBM traffic per launch from the FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a 256 MiB
 # copy), valid while the kernel source is the one that was measured.
 PMC_TRAFFIC = {
-    "ntt_fwd": {"source": "paper_2409_05205_amd/csrc/kernels_ntt.hip",
-                "sha256": "ef74afd2a0e95976aa551fa144b076fe777b22c7d2c24e449af46b7b76089e29",
-                "bytes_per_launch": 1832600},
+    # launches carrying the MAC in the plain form: k_mac_tail (conv) and k_mac_full (FC)
+    "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
+            "sha256": "064c6a0f68af9f3f479ce532e260bc7d746bd92091c9c34be62601723d9bf2d3",
+            "bytes_per_launch": 19733467},
+    "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
+                "sha256": "e80f7ad8bc1bf8e5aef93e5616d40f636d43b86631b0f7b17857bc1916500bf0",
+                "bytes_per_launch": 1826217},
 }
 
 
 def pmc_traffic(kind):
+    """Counter-measured HBM bytes per launch, or None once a measured source has changed."""
     import hashlib
     rec = PMC_TRAFFIC.get(kind)
     if rec is None:
         return None
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
-            return None
-    return rec["bytes_per_launch"]
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["sha256"] else None
 
 
 def log(*a):
@@ -379,7 +385,7 @@ def main():
     n_fused = plan.count("fused")
     roof_mac = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": pmc_traffic("mac_tail") if n_fused == n_layers - 1 else None,
+                "traffic": pmc_traffic("mac") if n_fused == n_layers - 1 else None,
                 "algorithmic_bytes_per_launch": mac_bytes // mac_launches_per_step,
                 "kernel": f"k_mac_tail (fused MAC + residue-class inverse, {n_fused} layers) / "
                           f"k_mac_class, k_mac_full (split MAC, {n_layers - n_fused} layers)",
@@ -415,7 +421,7 @@ def main():
                    "form": "plain: native runtime issues the 20 layer calls back to back on one stream"},
         "limb_poly_macs_per_s": round(st.modmuls() / 8192 * args.steps / T_plain, 1),
         "roofline": roofline,
-        "roofline_mac": roof_mac,
+        "rooflines": {"mac": roof_mac, "ntt_fwd": roof_fwd},
         "dominant_kernel": dominant,
         "kernels": kern,
         "forms": {

@@ -298,7 +298,8 @@ void he_server_free(he_server *srv);
  * sweep all values with it).  he_autotune_layer tunes the knobs of one layer at
  * batch B one after another: each candidate is timed as a whole layer call on
  * scratch buffers (median of 5, caches evicted before each), and the fastest is
- * kept for later calls with that shape.  It allocates and frees its scratch
+ * kept for later calls with that shape (at B = 1 the MAC form is not tuned: the
+ * fused launch is kept).  It allocates and frees its scratch
  * (about 512 MiB plus one call's buffers) and synchronises the stream.
  * he_tune_get reads a kept choice back (key: knob, log2 of the transform size,
  * rows per launch; for HE_TUNE_MAC the layer and B).

@@ -472,10 +472,12 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
     if (rc == HE_OK) rc = pick(HE_TUNE_NTT_FWD, logN, 2 * fwd_rows, radix, true);
     if (conv) {
         const bool cls = in.flags == HE_PACK_CLASS_INTT;
+        // batch one keeps the fused form (one launch per layer); batches try every form
         std::vector<int> macs{0};
         if (mac_tiled_ok(ly, B)) macs.push_back(1);
         if (mac_fused_ok(ctx, ly)) macs.push_back(2);
         if (mac_lds_ok(ly, B)) macs.push_back(3);
+        if (B == 1) macs.clear();
         if (rc == HE_OK && macs.size() > 1) rc = pick(HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B, macs, true);
         const uint32_t logm = logN - log2u(in.s);
         const uint32_t rows = B * in.K_out * in.g_o * L;
