@@ -202,6 +202,13 @@ int he_profile_reset(he_ctx *ctx);
  * (the masks of the server initialisation) and X = v, Y = i this is the
  * client's c1^r (Alg. 1 / Alg. 2 client evaluation); pass d_sh_next = NULL.
  *
+ * he_client_masks -- the client's layer of the same form built on the device
+ * from a server layer (he_pack_filters) and the client's key and noise: p1 =
+ * rho b + e1 and p2 = Delta (fhat + rho) + e2 for every (j, n) (Alg. 1 / Alg. 2
+ * server initialisation), kept NTT-domain like he_pack_operands(p1, p2).  b:
+ * device [L][N] residues (public key part); e1, e2: device int32, conv
+ * [K_in][c_o][N], fc [blocks][N], small signed.  The server layer is only read.
+ *
  * he_encrypt_c0 -- c0 of the encryption of -msg (Alg. 1 / Alg. 2 client
  * encryption, Eq. encryption negated): out[r] = -(v[r] b + Delta msg[r] + e0[r])
  * mod q_l.  v, e0: device int32 [rows][N] (small signed), b: device [L][N]
@@ -218,6 +225,8 @@ int he_profile_reset(he_ctx *ctx);
  */
 int he_pack_operands(he_ctx *ctx, const he_layer_desc *desc, const uint32_t *a, const uint32_t *b,
                      uint32_t flags, he_layer **out);
+int he_client_masks(he_ctx *ctx, const he_layer *server, const uint32_t *d_b, const int32_t *d_e1,
+                    const int32_t *d_e2, he_layer **out);
 int he_encrypt_c0(he_ctx *ctx, uint32_t rows, const int32_t *d_v, const uint32_t *d_b,
                   const uint32_t *d_msg, const int32_t *d_e0, uint32_t *d_out, void *stream);
 int he_decrypt(he_ctx *ctx, uint32_t rows, uint32_t M, const uint32_t *d_x0, const uint32_t *d_x1,

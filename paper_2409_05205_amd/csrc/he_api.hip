@@ -837,6 +837,76 @@ int he_pack_operands(he_ctx *ctx, const he_layer_desc *desc, const uint32_t *a, 
     return HE_OK;
 }
 
+int he_client_masks(he_ctx *ctx, const he_layer *server, const uint32_t *d_b, const int32_t *d_e1,
+                    const int32_t *d_e2, he_layer **out) {
+    if (!ctx || !server || server->ctx != ctx || !d_b || !d_e1 || !d_e2 || !out) return HE_EINVAL;
+    const he_layer_info &in = server->info;
+    const uint32_t N = ctx->N, L = ctx->L, K_in = in.K_in, Jtot = 2 * K_in, n_rows = server->n_rows;
+    he_layer *ly = new (std::nothrow) he_layer();
+    if (!ly) return HE_ENOMEM;
+    ly->ctx = ctx;
+    ly->n_rows = n_rows;
+    ly->info = in;
+    const size_t op_words = (size_t)n_rows * L * Jtot * N;
+    uint32_t *d_cls = nullptr, *bhat = nullptr;
+    auto fail = [&](hipError_t err, const char *what) {
+        hipFree(d_cls);
+        hipFree(bhat);
+        he_free_layer(ly);
+        return dev_fail(err, what);
+    };
+    hipError_t e;
+    if ((e = hipMalloc((void **)&ly->op, op_words * 4)) != hipSuccess || 
+        (e = hipMalloc((void **)&bhat, (size_t)L * N * 4)) != hipSuccess) {
+        hipFree(bhat);
+        he_free_layer(ly);
+        return HE_ENOMEM;
+    }
+    if (in.kind == HE_LAYER_FC) {
+        // the client's share carries no bias
+        const size_t nb = (size_t)in.blocks * in.n_o_p;
+        if ((e = hipMalloc((void **)&ly->bias, nb * 4)) != hipSuccess) return fail(e, "client masks bias");
+        if ((e = hipMemsetAsync(ly->bias, 0, nb * 4, nullptr)) != hipSuccess) return fail(e, "client masks bias");
+        ly->info.resident_bytes = op_words * 4 + nb * 4;
+    }
+    // f NTT(e1), f NTT(e2) in the operand layout, f the server layer's factor
+    if ((e = launch_mask_noise(d_e1, d_e2, ly->op, K_in, n_rows, L, N, ctx->lc, nullptr)) != hipSuccess)
+        return fail(e, "client masks noise");
+    RowMap m;
+    m.J = Jtot;
+    m.L = L;
+    m.src_b = m.dst_b = (uint64_t)L * Jtot * N;
+    m.src_j = m.dst_j = N;
+    m.src_l = m.dst_l = (uint64_t)Jtot * N;
+    if ((e = launch_ntt_fwd((int)ctx->logN, ly->op, ly->op, m, n_rows * Jtot * L, ctx->tw, ctx->twsh, ctx->lc,
+                            nullptr)) != hipSuccess)
+        return fail(e, "client masks noise ntt");
+    if (in.kind == HE_LAYER_CONV && in.flags == HE_PACK_CLASS_INTT) {
+        std::vector<uint32_t> cls(n_rows);
+        for (uint32_t n = 0; n < n_rows; ++n) cls[n] = (n % in.g_o) * (in.s / in.g_o);
+        if ((e = hipMalloc((void **)&d_cls, cls.size() * 4)) != hipSuccess) return fail(e, "client masks cls");
+        if ((e = hipMemcpy(d_cls, cls.data(), cls.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(e, "client masks cls copy");
+    }
+    if ((e = launch_scale_operands(ly->op, ctx->xinv, d_cls, Jtot, n_rows, L, N, ctx->lc, nullptr)) != hipSuccess)
+        return fail(e, "client masks scale");
+    // NTT(b), then the masks from the server's f NTT(rho), f NTT(-Delta fhat)
+    RowMap mb;
+    std::memset(&mb, 0, sizeof(mb));
+    mb.J = 1;
+    mb.L = L;
+    mb.src_l = mb.dst_l = N;
+    if ((e = launch_ntt_fwd((int)ctx->logN, d_b, bhat, mb, L, ctx->tw, ctx->twsh, ctx->lc, nullptr)) != hipSuccess)
+        return fail(e, "client masks ntt(b)");
+    if ((e = launch_mask_combine(server->op, bhat, ly->op, K_in, n_rows, L, N, ctx->lc, nullptr)) != hipSuccess)
+        return fail(e, "client masks combine");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(e, "client masks sync");
+    hipFree(d_cls);
+    hipFree(bhat);
+    *out = ly;
+    return HE_OK;
+}
+
 int he_encrypt_c0(he_ctx *ctx, uint32_t rows, const int32_t *d_v, const uint32_t *d_b, const uint32_t *d_msg,
                   const int32_t *d_e0, uint32_t *d_out, void *stream) {
     if (!ctx) return HE_EINVAL;

@@ -121,6 +121,13 @@ hipError_t launch_mac_tail(const uint32_t *X, const uint32_t *Op, uint32_t *out,
                            uint32_t N, uint32_t s, const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
                            hipStream_t st, const LaunchEv *ev = nullptr);
 
+// Client masks from the server's resident operands (kernels_client.hip): noise rows into the
+// operand layout, then the combination with NTT(b) (in place on E).
+hipError_t launch_mask_noise(const int32_t *e1, const int32_t *e2, uint32_t *E, uint32_t K_in, uint32_t n_rows,
+                             uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st);
+hipError_t launch_mask_combine(const uint32_t *S, const uint32_t *bhat, uint32_t *E, uint32_t K_in, uint32_t n_rows,
+                               uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st);
+
 // Client-side element-wise kernels (kernels_client.hip).
 struct DecConsts {
     uint32_t t;

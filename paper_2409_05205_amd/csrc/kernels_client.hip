@@ -80,6 +80,50 @@ __global__ void k_decrypt(const uint32_t *__restrict__ x0, const uint32_t *__res
     msg[(size_t)r * N + k] = (uint32_t)(whole % t);
 }
 
+
+// Client masks of the server initialisation (Alg. 1 / Alg. 2): from the
+// server's resident operands S[n][l][J][N] (J < K_in: f NTT(rho_j^(n)),
+// J >= K_in: f NTT(-Delta fhat_j^(n)), f the layer's per-slot factor) and the
+// client's public key NTT(b), the client operands
+//   J < K_in : f NTT(p1) = S_J bhat + f NTT(e1),   p1 = rho b + e1
+//   J >= K_in: f NTT(p2) = Delta S_{J-K_in} - S_J + f NTT(e2),   p2 = Delta (fhat + rho) + e2
+// where E already holds f NTT(e1) / f NTT(e2) and is overwritten with the result.
+__global__ void k_mask_combine(const uint32_t *__restrict__ S, const uint32_t *__restrict__ bhat,
+                               uint32_t *__restrict__ E, uint32_t K_in, uint32_t L, uint32_t N, LimbConsts lc) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t Jtot = 2 * K_in;
+    const uint32_t row = blockIdx.y;          // (n, l, J)
+    const uint32_t J = row % Jtot;
+    const uint32_t l = (row / Jtot) % L;
+    const LimbConst c = lc.l[l];
+    const size_t i = (size_t)row * N + k;
+    uint32_t v;
+    if (J < K_in) {
+        v = reduce64((uint64_t)S[i] * bhat[(size_t)l * N + k] + E[i], c);
+    } else {
+        const uint32_t dr = reduce64((uint64_t)S[i - (size_t)K_in * N] * c.delta, c);   // Delta f NTT(rho)
+        v = reduce64((uint64_t)dr + (c.q - S[i]) + E[i], c);
+    }
+    E[i] = v;
+}
+
+// E[n][l][J][k] = e[J][n][k] mod q_l: the mask noise of channel n (J < K_in: e1, else e2),
+// small signed values, laid out like the resident operands.
+__global__ void k_mask_noise(const int32_t *__restrict__ e1, const int32_t *__restrict__ e2, uint32_t *__restrict__ E,
+                             uint32_t K_in, uint32_t n_rows, uint32_t L, uint32_t N, LimbConsts lc) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t Jtot = 2 * K_in;
+    const uint32_t row = blockIdx.y;
+    const uint32_t J = row % Jtot;
+    const uint32_t l = (row / Jtot) % L;
+    const uint32_t n = row / (Jtot * L);
+    const uint32_t q = lc.l[l].q;
+    const int32_t x = J < K_in ? e1[((size_t)J * n_rows + n) * N + k] : e2[((size_t)(J - K_in) * n_rows + n) * N + k];
+    const int64_t r = (int64_t)x % (int64_t)q;
+    E[(size_t)row * N + k] = (uint32_t)(r < 0 ? r + q : r);
+}
 }  // namespace
 
 hipError_t launch_lift_signed(const int32_t *a, uint32_t *out, uint32_t rows, uint32_t L, uint32_t N,
@@ -108,5 +152,19 @@ hipError_t launch_decrypt(const uint32_t *x0, const uint32_t *x1, uint32_t *msg,
                           const LimbConsts &lc, const DecConsts &dc, hipStream_t st) {
     if (!rows) return hipSuccess;
     hipLaunchKernelGGL(k_decrypt, dim3((N + 255) / 256, rows), dim3(256), 0, st, x0, x1, msg, L, N, lc, dc);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_noise(const int32_t *e1, const int32_t *e2, uint32_t *E, uint32_t K_in, uint32_t n_rows,
+                             uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st) {
+    dim3 grid((N + 255) / 256, n_rows * L * 2 * K_in);
+    hipLaunchKernelGGL(k_mask_noise, grid, dim3(256), 0, st, e1, e2, E, K_in, n_rows, L, N, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_combine(const uint32_t *S, const uint32_t *bhat, uint32_t *E, uint32_t K_in, uint32_t n_rows,
+                               uint32_t L, uint32_t N, const LimbConsts &lc, hipStream_t st) {
+    dim3 grid((N + 255) / 256, n_rows * L * 2 * K_in);
+    hipLaunchKernelGGL(k_mask_combine, grid, dim3(256), 0, st, S, bhat, E, K_in, L, N, lc);
     return hipGetLastError();
 }

@@ -32,7 +32,7 @@ EXPORTED = [
     "he_server_create", "he_server_add_layer", "he_server_add_request", "he_server_run", "he_server_requests",
     "he_server_results", "he_server_free",
     "he_tune_force", "he_autotune_layer", "he_tune_get",
-    "he_pack_operands", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
+    "he_pack_operands", "he_client_masks", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
 ]
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
 HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL = 1, 2, 4, 8, 16
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_server_results.argtypes = [VP, D, D, D, P(U32), P(ctypes.c_int32)]
     lib.he_server_free.argtypes = [VP]
     lib.he_pack_operands.argtypes = [VP, P(LayerDesc), VP, VP, U32, P(VP)]
+    lib.he_client_masks.argtypes = [VP, VP, VP, VP, VP, P(VP)]
     lib.he_encrypt_c0.argtypes = [VP, U32, VP, VP, VP, VP, VP, VP]
     lib.he_decrypt.argtypes = [VP, U32, U32, VP, VP, VP, VP]
     lib.he_tune_force.argtypes = [VP, U32, ctypes.c_int32]
@@ -185,10 +186,11 @@ class FCSpec:
 class Layer:
     """A packed layer: NTT-domain operands resident on the device."""
 
-    def __init__(self, ctx: "Context", handle: int, kind: int):
+    def __init__(self, ctx: "Context", handle: int, kind: int, rows: int):
         self.ctx = ctx
         self.handle = ctypes.c_void_p(handle)
         self.kind = kind
+        self.rows = rows          # output channels (conv) or row blocks (fc)
         info = LayerInfo()
         _check(load_library().he_layer_info_get(self.handle, ctypes.byref(info)), "he_layer_info_get")
         self.info = info
@@ -243,7 +245,7 @@ class Context:
         h = ctypes.c_void_p()
         _check(load_library().he_pack_filters(self.handle, ctypes.byref(d), w.ctypes.data, r.ctypes.data, None,
                                               flags, ctypes.byref(h)), "he_pack_filters")
-        return Layer(self, h.value, HE_LAYER_CONV)
+        return Layer(self, h.value, HE_LAYER_CONV, spec.c_o)
 
     def pack_fc(self, spec, weights: np.ndarray, rho: np.ndarray, bias: Optional[np.ndarray] = None) -> Layer:
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.int8))
@@ -256,7 +258,9 @@ class Context:
         _check(load_library().he_pack_filters(self.handle, ctypes.byref(d), w.ctypes.data, r.ctypes.data,
                                               None if b is None else b.ctypes.data, 0, ctypes.byref(h)),
                "he_pack_filters")
-        return Layer(self, h.value, HE_LAYER_FC)
+        layer = Layer(self, h.value, HE_LAYER_FC, 0)
+        layer.rows = layer.info.blocks
+        return layer
 
     def pack_operands(self, spec, a: np.ndarray, b: np.ndarray, flags: int = HE_PACK_CLASS_INTT) -> Layer:
         """A layer with resident operands NTT(a), NTT(b) (e.g. the client masks p1, p2).
@@ -276,7 +280,24 @@ class Context:
         h = ctypes.c_void_p()
         _check(load_library().he_pack_operands(self.handle, ctypes.byref(d), a.ctypes.data, b.ctypes.data, flags,
                                                ctypes.byref(h)), "he_pack_operands")
-        return Layer(self, h.value, kind)
+        layer = Layer(self, h.value, kind, spec.c_o if kind == HE_LAYER_CONV else 0)
+        if kind == HE_LAYER_FC:
+            layer.rows = layer.info.blocks
+        return layer
+
+    def client_masks(self, server: "Layer", b, e1, e2) -> "Layer":
+        """The client's layer for `server` built on the device: masks p1 = rho b + e1 and
+        p2 = Delta (fhat + rho) + e2.  b: device int32 [L][N] residues; e1, e2: device int32
+        [K_in][c_o][N] (conv) or [blocks][N] (fc)."""
+        i = server.info
+        shp = (i.K_in, server.rows, self.N) if server.kind == HE_LAYER_CONV else (i.blocks, self.N)
+        _check_dev(b, (self.L, self.N), "b")
+        _check_dev(e1, shp, "e1")
+        _check_dev(e2, shp, "e2")
+        h = ctypes.c_void_p()
+        _check(load_library().he_client_masks(self.handle, server.handle, _ptr(b), _ptr(e1), _ptr(e2),
+                                              ctypes.byref(h)), "he_client_masks")
+        return Layer(self, h.value, server.kind, server.rows)
 
     def encrypt_c0(self, v, b, msg, e0, out=None, stream=None):
         """out = -(v b + Delta msg + e0) per limb; v, e0 int32 [rows][N], b [L][N], msg [rows][N] < t."""

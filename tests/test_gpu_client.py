@@ -1,7 +1,7 @@
-"""GPU client role: c0 encryption, key generation, decryption and the client's
-c1^r layer (masks p1, p2 as resident operands), each bit-exact against the
-oracle's client, and a layer that goes through every party on the device and
-decrypts to the integer convolution."""
+"""GPU client role: c0 encryption, key generation, decryption, the client's
+masks p1, p2 built on the device from the server layer, and the client's c1^r
+layer, each bit-exact against the oracle's client, and a layer that goes
+through every party on the device and decrypts to the integer convolution."""
 import numpy as np
 import pytest
 
@@ -139,11 +139,63 @@ def test_every_party_on_device_decrypts(he):
     c0 = ctx.encrypt_c0(dev(v), b, dev(i), dev(e0))
     server = ctx.pack_conv(he.ConvSpec(3, 16, 32, 32), F, rho)
     c0r = ctx.conv_layer(server, c0[None], dev(sh[None]), dev(shn[None]))[0]
-    p1, p2 = bfv.client_masks(octx, rho, fh, host(b[None])[0], wl.gaussian(rng, (g.K_in, 16, N)),
-                              wl.gaussian(rng, (g.K_in, 16, N)))
-    client = ctx.pack_operands(he.ConvSpec(3, 16, 32, 32), p1, p2)
+    client = ctx.client_masks(server, b, dev(wl.gaussian(rng, (g.K_in, 16, N))), dev(wl.gaussian(rng, (g.K_in, 16, N))))
     vres = np.stack([np.stack([v[j] % q for q in octx.primes]) for j in range(g.K_in)])
     c1r = ctx.conv_layer(client, dev(vres[None]), dev(i[None]))[0]
     r = host(ctx.decrypt(c0r, c1r)).astype(np.int64)
     dec = network.centred(packing.decode_conv_output((r - shn) % T, g), T)
     assert (dec == network.conv2d(img, F)).all()
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_client_masks_on_device_match_oracle(he, flags):
+    """Masks p1 = rho b + e1, p2 = Delta (fhat + rho) + e2 formed on the device from the server
+    layer's resident operands: the client layer they give equals the oracle client's c1^r."""
+    N, L = 1024, 2
+    ctx = he.Context(N, L, T)
+    octx = bfv.make_ctx(N, L, T)
+    g = packing.conv_geometry(N, 20, 24, 6, 6)
+    rng = np.random.default_rng(31 + flags)
+    F = rng.integers(-7, 8, (24, 20, 3, 3))
+    fh = packing.pack_conv_filters(F, g)
+    rho = rng.integers(0, T, (g.K_in, 24, N))
+    _, _, _, b = _keys(octx, 7)
+    e1 = wl.gaussian(rng, (g.K_in, 24, N))
+    e2 = wl.gaussian(rng, (g.K_in, 24, N))
+    p1, p2 = bfv.client_masks(octx, rho, fh, b, e1, e2)
+    v = wl.encryption_v(rng, (g.K_in, N))
+    i = rng.integers(0, T, (g.K_in, N))
+    want = bfv.client_conv(octx, g, v, i, p1, p2)
+    server = ctx.pack_conv(he.ConvSpec(20, 24, 6, 6), F, rho, flags)
+    client = ctx.client_masks(server, dev(b), dev(e1), dev(e2))
+    vres = np.stack([np.stack([v[j] % q for q in octx.primes]) for j in range(g.K_in)])
+    got = host(ctx.conv_layer(client, dev(vres[None]), dev(i[None])))[0]
+    assert (got == want).all()
+    # the server layer is unchanged
+    sh = rng.integers(0, T, (g.K_in, N))
+    c0 = wl.uniform_per_modulus(rng, (g.K_in,), octx.primes, N)
+    got_s = host(ctx.conv_layer(server, dev(c0[None]), dev(sh[None])))[0]
+    assert (got_s == bfv.server_conv(octx, g, c0.astype(np.uint64), rho, fh, sh, None)).all()
+
+
+def test_client_fc_masks_on_device_match_oracle(he):
+    N, L = 1024, 2
+    ctx = he.Context(N, L, T)
+    octx = bfv.make_ctx(N, L, T)
+    g = packing.fc_geometry(N, 100, 7)
+    rng = np.random.default_rng(37)
+    W = rng.integers(-7, 8, (7, 100))
+    w = packing.pack_fc_weights(W, g)
+    rho = rng.integers(0, T, (g.blocks, N))
+    _, _, _, b = _keys(octx, 8)
+    e1 = wl.gaussian(rng, (g.blocks, N))
+    e2 = wl.gaussian(rng, (g.blocks, N))
+    p1, p2 = bfv.client_masks(octx, rho, w, b, e1, e2)
+    v = wl.encryption_v(rng, N)
+    i = rng.integers(0, T, N)
+    want = bfv.client_fc(octx, g, v, i, p1, p2)
+    server = ctx.pack_fc(he.FCSpec(100, 7), W, rho, rng.integers(-7, 8, 7))
+    client = ctx.client_masks(server, dev(b), dev(e1), dev(e2))
+    vres = np.stack([v % q for q in octx.primes])
+    got = host(ctx.fc_layer(client, dev(vres[None]), dev(i[None])))[0]
+    assert (got == want).all()
