@@ -252,6 +252,45 @@ def batched_rooflines(he, ctx, st, stream, sync, passes=2):
     return out
 
 
+def paper_protocol_form(he, ctx, st, stream, steps, warmup, sync):
+    """Seconds for `steps` images of the stack under the paper's protocol (see the caller): the
+    server's share transforms run as one chain on a second stream, each layer waiting only for
+    the transform of its own share."""
+    import torch
+    side = torch.cuda.Stream()
+    n = len(st.steps)
+    xs, outs = [], [None] * n
+    for ly, B, c0, sh, shn in st.steps:
+        x = ctx.input_buffer(ly, B)
+        ctx.inputs_ntt(ly, x, c0=c0)              # the client's NTT(c0), before timing
+        xs.append(x)
+    ready = [torch.cuda.Event() if st.steps[k][3] is not None else None for k in range(n)]
+
+    def body():
+        main = torch.cuda.current_stream()
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            for k, (ly, B, c0, sh, shn) in enumerate(st.steps):
+                if sh is not None:
+                    ctx.inputs_ntt(ly, xs[k], sh=sh)
+                    ready[k].record(side)
+        for k, (ly, B, c0, sh, shn) in enumerate(st.steps):
+            if ready[k] is not None:
+                main.wait_event(ready[k])
+            outs[k] = ctx.layer_from_ntt(ly, xs[k], sh is not None, shn, out=outs[k])
+        main.wait_stream(side)
+    # an eager pass allocates every workspace and output before the capture
+    with torch.cuda.stream(stream):
+        body()
+    sync()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        body()
+    sync()
+    with torch.cuda.stream(stream):
+        return time_loop(g.replay, steps, warmup, sync)
+
+
 # ------------------------------------------------------------------ CPU baseline
 def cpu_baseline(n_layers=3):
     """The oracle's server evaluation of the first layers of the x1 stack on host cores."""
@@ -357,6 +396,13 @@ def main():
         T_graph = time_loop(lambda: seq_g.replay(stream), args.steps, args.warmup, sync)
     log(f"graph: {T_graph / args.steps * 1e3:.3f} ms/step")
 
+    # paper_protocol: the same stack and calls under the paper's protocol (Sec. IV-A-1). The client
+    # sends NTT(c0) (its transform is client work, done before timing); the server draws its shares
+    # and transforms them on a second stream, ahead of the layers that read them, and each layer is
+    # then one launch on the main stream. Captured once into a graph, one replay per image.
+    T_proto = paper_protocol_form(he, ctx, st, stream, args.steps, args.warmup, sync)
+    log(f"paper_protocol: {T_proto / args.steps * 1e3:.3f} ms/step")
+
     # plain_host: per-layer Python calls with a sync after each layer, per-layer latency
     lat = []
 
@@ -427,6 +473,11 @@ def main():
         "forms": {
             "plain": {"layers_per_s": round(layers_per_s, 1), "ms_per_image": round(T_plain / args.steps * 1e3, 4)},
             "graph": {"layers_per_s": round(graph_lps, 1), "ms_per_image": round(T_graph / args.steps * 1e3, 4)},
+            "paper_protocol": {"layers_per_s": round(n_layers * args.steps / T_proto, 1),
+                               "ms_per_image": round(T_proto / args.steps * 1e3, 4),
+                               "note": "c0 arrives as NTT(c0) (client's transform, untimed); the server's "
+                                       "NTT(sh) of every layer runs as a chain on a second stream, each "
+                                       "layer waiting for its own"},
             "plain_host": {"layers_per_s": round(n_layers * host_steps / T_host, 1),
                            "ms_per_image": round(T_host / host_steps * 1e3, 4),
                            "layer_latency_p50_ms": round(percentile(lat, 50) * 1e3, 4),

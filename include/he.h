@@ -163,6 +163,31 @@ int he_fc_layer_ws(he_ctx *ctx, const he_layer *layer, uint32_t B,
                    uint32_t *d_out, void *d_workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * The same layer split at its NTT-domain inputs, as the paper's protocol runs
+ * it (Sec. IV-A-1): the client obtains NTT(c0) during encryption and sends it;
+ * the server computes NTT(sh) of its own share, which it can do as soon as it
+ * draws the share, before the layer's c0 arrives.
+ *
+ * he_layer_inputs_ntt -- forward NTTs of c0 and/or sh (either may be NULL) of
+ * B images into the layer's NTT-domain input buffer d_x [B][2 K_in][L][N]
+ * (device, 16-byte aligned, caller-owned): c0 rows at [b][j], sh rows at
+ * [b][K_in + j]; K_in = 1 for FC.  d_c0 and d_sh as for he_conv_layer /
+ * he_fc_layer.  Rows not passed are left as they are.
+ *
+ * he_conv_layer_ntt / he_fc_layer_ntt -- the rest of the layer (MAC, inverse,
+ * extraction, + Delta sh') from d_x; has_sh = 0 when the layer has no input
+ * share (the sh rows of d_x are then not read).  d_sh_next, d_out as for
+ * he_conv_layer / he_fc_layer.  Uses the context workspace of the stream.
+ * he_conv_layer is he_layer_inputs_ntt followed by he_conv_layer_ntt (same words).
+ */
+int he_layer_inputs_ntt(he_ctx *ctx, const he_layer *layer, uint32_t B, const uint32_t *d_c0,
+                        const uint32_t *d_sh, uint32_t *d_x, void *stream);
+int he_conv_layer_ntt(he_ctx *ctx, const he_layer *layer, uint32_t B, const uint32_t *d_x, int has_sh,
+                      const uint32_t *d_sh_next, uint32_t *d_out, void *stream);
+int he_fc_layer_ntt(he_ctx *ctx, const he_layer *layer, uint32_t B, const uint32_t *d_x, int has_sh,
+                    const uint32_t *d_sh_next, uint32_t *d_out, void *stream);
+
+/*
  * Transform primitives on device polynomials, exposed for checking the ring
  * arithmetic (Sec. IV-A-1: products through NTTs and coefficient-wise
  * multiplications).  d_in / d_out: [rows][L][N] u32 residues < q_l; may alias.
@@ -302,8 +327,8 @@ void he_server_free(he_server *srv);
  * 1 (register-blocked batched MAC), 2 (residue-class conv layers: MAC, inverse
  * and extraction fused, one workgroup per output row), 3 (residue-class conv
  * layers, B >= 2: LDS-staged batched MAC over image x channel tiles) or -1
- * (automatic: 2 at B = 1, 1 at B >= 4); a value the layer's shape does not
- * allow falls back to 0.  Every value yields the same output words.  he_tune_force pins a knob for the whole context (tests
+ * (automatic: 2 at B = 1; at B >= 4, 3 for residue-class layers and 1 for
+ * full-length ones); a value the layer's shape does not allow falls back to 0.  Every value yields the same output words.  he_tune_force pins a knob for the whole context (tests
  * sweep all values with it).  he_autotune_layer tunes the knobs of one layer at
  * batch B one after another: each candidate is timed as a whole layer call on
  * scratch buffers (median of 5, caches evicted before each), and the fastest is

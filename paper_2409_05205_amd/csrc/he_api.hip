@@ -190,9 +190,10 @@ int knob(he_ctx *ctx, int which, uint32_t logsize, uint32_t rows) {
 }
 
 // Conv MAC variant of a layer at batch B: 0 streaming (then tail), 1 register-blocked
-// batched (then tail), 2 fused MAC + residue-class tail.  A tuned or forced value is
-// used when the layer's shape allows it; otherwise, and by default, B = 1 takes the
-// fused form and B >= 4 the batched one.
+// batched (then tail), 2 fused MAC + residue-class tail, 3 LDS-staged batched (then
+// tail).  A tuned or forced value is used when the layer's shape allows it; otherwise,
+// and by default, B = 1 takes the fused form and B >= 4 a batched one (3 for the
+// residue-class form, 1 for the full-length form).
 bool mac_tiled_ok(const he_layer *ly, uint32_t B) {
     const he_layer_info &in = ly->info;
     const bool cls = in.flags == HE_PACK_CLASS_INTT;
@@ -218,6 +219,7 @@ int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
     if (mk == 1) return tiled_ok ? 1 : 0;
     if (mk == 0) return 0;
     if (B == 1 && fused_ok) return 2;
+    if (B >= 4 && mac_lds_ok(ly, B)) return 3;
     return tiled_ok && B >= 4 ? 1 : 0;
 }
 
@@ -954,50 +956,71 @@ int he_decrypt(he_ctx *ctx, uint32_t rows, uint32_t M, const uint32_t *d_x0, con
     return e == hipSuccess ? HE_OK : dev_fail(e, "decrypt");
 }
 
-int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
-                     const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, void *stream) {
-    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
-    if (B == 0) return HE_OK;
-    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
-    if (!aligned16(d_c0) || !aligned16(d_out) || !aligned16(d_ws)) return HE_EINVAL;
-    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
+namespace {
+
+size_t x_bytes(const he_layer *ly, uint32_t B) {
+    const he_layer_info &in = ly->info;
+    return align256((size_t)B * 2 * in.K_in * in.L * in.N * 4);
+}
+
+// a1: forward NTT of the c0 rows (b, j, l) and/or the sh rows (one coefficient row per (b, j),
+// read for every limb) into the NTT-domain input buffer x [B][2 K_in][L][N]: c0 at J < K_in,
+// sh at J >= K_in.  One launch.
+hipError_t inputs_ntt(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                      uint32_t *x, hipStream_t st) {
+    const he_layer_info &in = ly->info;
+    const uint32_t N = in.N, L = in.L, K_in = in.K_in, Jtot = 2 * K_in;
+    const int logN = (int)ctx->logN;
+    RowMap mc;
+    mc.J = K_in;
+    mc.L = L;
+    mc.src_b = (uint64_t)K_in * L * N;
+    mc.src_j = (uint64_t)L * N;
+    mc.src_l = N;
+    mc.dst_b = (uint64_t)Jtot * L * N;
+    mc.dst_j = (uint64_t)L * N;
+    mc.dst_l = N;
+    RowMap ms = mc;
+    ms.src_b = (uint64_t)K_in * N;
+    ms.src_j = N;
+    ms.src_l = 0;
+    FwdJobs jobs;
+    int nj = 0;
+    if (d_c0) {
+        jobs.src[nj] = d_c0;
+        jobs.dst[nj] = x;
+        jobs.map[nj] = mc;
+        ++nj;
+    }
+    if (d_sh) {
+        jobs.src[nj] = d_sh;
+        jobs.dst[nj] = x + (size_t)K_in * L * N;
+        jobs.map[nj] = ms;
+        ++nj;
+    }
+    if (nj == 0) return hipSuccess;
+    if (nj == 1) {
+        jobs.src[1] = jobs.src[0];
+        jobs.dst[1] = jobs.dst[0];
+        jobs.map[1] = jobs.map[0];
+    }
+    jobs.rows0 = B * K_in * L;
+    const uint32_t rows = jobs.rows0 * nj;
+    ProfScope ps(ctx, HE_K_NTT_FWD);
+    const hipError_t e = launch_ntt_fwd2(logN, knob(ctx, HE_TUNE_NTT_FWD, (uint32_t)logN, rows), jobs, rows, ctx->tw,
+                                         ctx->twsh, ctx->lc, st, ps.ev());
+    return ps.done(e);
+}
+
+// a2-a4 of a conv layer from the NTT-domain inputs x; mac: MAC-output workspace.
+int conv_from_x(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *xn, bool has_sh,
+                const uint32_t *d_sh_next, uint32_t *d_out, uint32_t *mac, hipStream_t st) {
     const he_layer_info &in = ly->info;
     const uint32_t N = in.N, L = in.L, K_in = in.K_in, Jtot = 2 * K_in, c_o = ly->n_rows;
     const int logN = (int)ctx->logN;
-    hipStream_t st = (hipStream_t)stream;
-    uint32_t *xn = (uint32_t *)d_ws;
-    uint32_t *mac = (uint32_t *)((char *)d_ws + align256((size_t)B * Jtot * L * N * 4));
     hipError_t e;
-
-    // a1: forward NTT of c0 (rows b, j, l) and, in the same launch, of sh (same coefficients every limb)
-    FwdJobs jobs;
-    RowMap &m = jobs.map[0];
-    m.J = K_in;
-    m.L = L;
-    m.src_b = (uint64_t)K_in * L * N;
-    m.src_j = (uint64_t)L * N;
-    m.src_l = N;
-    m.dst_b = (uint64_t)Jtot * L * N;
-    m.dst_j = (uint64_t)L * N;
-    m.dst_l = N;
-    jobs.src[0] = d_c0;
-    jobs.dst[0] = xn;
-    jobs.rows0 = B * K_in * L;
-    jobs.map[1] = m;
-    jobs.map[1].src_b = (uint64_t)K_in * N;
-    jobs.map[1].src_j = N;
-    jobs.map[1].src_l = 0;
-    jobs.src[1] = d_sh ? d_sh : d_c0;
-    jobs.dst[1] = xn + (size_t)K_in * L * N;
-    const uint32_t fwd_rows = jobs.rows0 * (d_sh ? 2 : 1);
-    {
-        ProfScope ps(ctx, HE_K_NTT_FWD);
-        e = launch_ntt_fwd2(logN, knob(ctx, HE_TUNE_NTT_FWD, (uint32_t)logN, fwd_rows), jobs, fwd_rows, ctx->tw,
-                            ctx->twsh, ctx->lc, st, ps.ev());
-        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "conv forward ntt");
-    }
     // a2: coefficient-wise MAC over the input rows
-    const uint32_t Juse = d_sh ? Jtot : K_in;
+    const uint32_t Juse = has_sh ? Jtot : K_in;
     const bool cls = in.flags == HE_PACK_CLASS_INTT;
     const int mk = mac_variant(ctx, ly, B);
     if (mk == 2) {
@@ -1054,59 +1077,16 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t
     return HE_OK;
 }
 
-int he_conv_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
-                  const uint32_t *d_sh_next, uint32_t *d_out, void *stream) {
-    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
-    if (B == 0) return HE_OK;
-    void *ws = nullptr;
-    const size_t need = layer_ws_bytes(ly, B);
-    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
-    if (rc != HE_OK) return rc;
-    return he_conv_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, stream);
-}
-
-int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
-                   const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, void *stream) {
-    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_FC) return HE_EINVAL;
-    if (B == 0) return HE_OK;
-    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
-    if (!aligned16(d_c0) || !aligned16(d_ws)) return HE_EINVAL;
-    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
+// a2-a5 of an FC layer from the NTT-domain inputs x; mac: MAC-output workspace.
+int fc_from_x(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *xn, bool has_sh,
+              const uint32_t *d_sh_next, uint32_t *d_out, uint32_t *mac, hipStream_t st) {
     const he_layer_info &in = ly->info;
     const uint32_t N = in.N, L = in.L;
     const int logN = (int)ctx->logN;
-    hipStream_t st = (hipStream_t)stream;
-    uint32_t *xn = (uint32_t *)d_ws;
-    uint32_t *mac = (uint32_t *)((char *)d_ws + align256((size_t)B * 2 * L * N * 4));
     hipError_t e;
-    FwdJobs jobs;
-    RowMap &m = jobs.map[0];
-    m.J = 1;
-    m.L = L;
-    m.src_b = (uint64_t)L * N;
-    m.src_j = 0;
-    m.src_l = N;
-    m.dst_b = (uint64_t)2 * L * N;
-    m.dst_j = 0;
-    m.dst_l = N;
-    jobs.src[0] = d_c0;
-    jobs.dst[0] = xn;
-    jobs.rows0 = B * L;
-    jobs.map[1] = m;
-    jobs.map[1].src_b = N;
-    jobs.map[1].src_l = 0;
-    jobs.src[1] = d_sh ? d_sh : d_c0;
-    jobs.dst[1] = xn + (size_t)L * N;
-    const uint32_t fwd_rows = jobs.rows0 * (d_sh ? 2 : 1);
-    {
-        ProfScope ps(ctx, HE_K_NTT_FWD);
-        e = launch_ntt_fwd2(logN, knob(ctx, HE_TUNE_NTT_FWD, (uint32_t)logN, fwd_rows), jobs, fwd_rows, ctx->tw,
-                            ctx->twsh, ctx->lc, st, ps.ev());
-        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "fc forward ntt");
-    }
     {
         ProfScope ps(ctx, HE_K_MAC);
-        e = launch_mac_full(xn, ly->op, mac, B, 2, d_sh ? 2 : 1, in.blocks, L, N, ctx->lc, st, ps.ev());
+        e = launch_mac_full(xn, ly->op, mac, B, 2, has_sh ? 2 : 1, in.blocks, L, N, ctx->lc, st, ps.ev());
         if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "fc mac");
     }
     EpiParams ep;
@@ -1130,6 +1110,49 @@ int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *
     return HE_OK;
 }
 
+}  // namespace
+
+int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                     const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
+    if (!aligned16(d_c0) || !aligned16(d_out) || !aligned16(d_ws)) return HE_EINVAL;
+    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *xn = (uint32_t *)d_ws;
+    uint32_t *mac = (uint32_t *)((char *)d_ws + x_bytes(ly, B));
+    const hipError_t e = inputs_ntt(ctx, ly, B, d_c0, d_sh, xn, st);
+    if (e != hipSuccess) return dev_fail(e, "conv forward ntt");
+    return conv_from_x(ctx, ly, B, xn, d_sh != nullptr, d_sh_next, d_out, mac, st);
+}
+
+int he_conv_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                  const uint32_t *d_sh_next, uint32_t *d_out, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    void *ws = nullptr;
+    const size_t need = layer_ws_bytes(ly, B);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
+    if (rc != HE_OK) return rc;
+    return he_conv_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, stream);
+}
+
+int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                   const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_FC) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
+    if (!aligned16(d_c0) || !aligned16(d_ws)) return HE_EINVAL;
+    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *xn = (uint32_t *)d_ws;
+    uint32_t *mac = (uint32_t *)((char *)d_ws + x_bytes(ly, B));
+    const hipError_t e = inputs_ntt(ctx, ly, B, d_c0, d_sh, xn, st);
+    if (e != hipSuccess) return dev_fail(e, "fc forward ntt");
+    return fc_from_x(ctx, ly, B, xn, d_sh != nullptr, d_sh_next, d_out, mac, st);
+}
+
 int he_fc_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
                 const uint32_t *d_sh_next, uint32_t *d_out, void *stream) {
     if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_FC) return HE_EINVAL;
@@ -1139,6 +1162,39 @@ int he_fc_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c
     int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
     if (rc != HE_OK) return rc;
     return he_fc_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, stream);
+}
+
+int he_layer_inputs_ntt(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                        uint32_t *d_x, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || !d_x) return HE_EINVAL;
+    if (B == 0 || (!d_c0 && !d_sh)) return HE_OK;
+    if (!aligned16(d_x) || (d_c0 && !aligned16(d_c0))) return HE_EINVAL;
+    const hipError_t e = inputs_ntt(ctx, ly, B, d_c0, d_sh, d_x, (hipStream_t)stream);
+    return e == hipSuccess ? HE_OK : dev_fail(e, "layer input ntt");
+}
+
+int he_conv_layer_ntt(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_x, int has_sh,
+                      const uint32_t *d_sh_next, uint32_t *d_out, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    if (!d_x || !d_out || !aligned16(d_x) || !aligned16(d_out)) return HE_EINVAL;
+    void *ws = nullptr;
+    const size_t need = layer_ws_bytes(ly, B) - x_bytes(ly, B);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need > 0 ? need : 256, &ws);
+    if (rc != HE_OK) return rc;
+    return conv_from_x(ctx, ly, B, d_x, has_sh != 0, d_sh_next, d_out, (uint32_t *)ws, (hipStream_t)stream);
+}
+
+int he_fc_layer_ntt(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_x, int has_sh,
+                    const uint32_t *d_sh_next, uint32_t *d_out, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_FC) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    if (!d_x || !d_out || !aligned16(d_x)) return HE_EINVAL;
+    void *ws = nullptr;
+    const size_t need = layer_ws_bytes(ly, B) - x_bytes(ly, B);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
+    if (rc != HE_OK) return rc;
+    return fc_from_x(ctx, ly, B, d_x, has_sh != 0, d_sh_next, d_out, (uint32_t *)ws, (hipStream_t)stream);
 }
 
 int he_ntt_forward(he_ctx *ctx, uint32_t rows, const uint32_t *d_in, uint32_t *d_out, void *stream) {

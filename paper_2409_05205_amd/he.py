@@ -32,6 +32,7 @@ EXPORTED = [
     "he_server_create", "he_server_add_layer", "he_server_add_request", "he_server_run", "he_server_requests",
     "he_server_results", "he_server_free",
     "he_tune_force", "he_autotune_layer", "he_tune_get",
+    "he_layer_inputs_ntt", "he_conv_layer_ntt", "he_fc_layer_ntt",
     "he_pack_operands", "he_client_masks", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
 ]
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
@@ -90,6 +91,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
     for name in ("he_conv_layer_ws", "he_fc_layer_ws"):
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP, SZ, VP]
+    lib.he_layer_inputs_ntt.argtypes = [VP, VP, U32, VP, VP, VP, VP]
+    for name in ("he_conv_layer_ntt", "he_fc_layer_ntt"):
+        getattr(lib, name).argtypes = [VP, VP, U32, VP, ctypes.c_int, VP, VP, VP]
     lib.he_ntt_forward.argtypes = [VP, U32, VP, VP, VP]
     lib.he_ntt_inverse.argtypes = [VP, U32, VP, VP, VP]
     lib.he_poly_mul.argtypes = [VP, U32, VP, VP, VP, VP]
@@ -373,6 +377,50 @@ class Context:
             rc = lib.he_fc_layer_ws(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out),
                                     _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream))
         _check(rc, "he_fc_layer")
+        return out
+
+    # ---------------------------------------------------------- NTT-domain inputs (paper's protocol)
+    def input_buffer(self, layer: Layer, B: int):
+        """An NTT-domain input buffer [B][2 K_in][L][N] for `layer`."""
+        import torch
+        return torch.empty((B, 2 * layer.info.K_in, self.L, self.N), dtype=torch.int32, device="cuda")
+
+    def inputs_ntt(self, layer: Layer, x, c0=None, sh=None, stream=None):
+        """Forward NTTs of c0 and/or sh into x (he_layer_inputs_ntt); returns x."""
+        B = x.shape[0]
+        i = layer.info
+        _check_dev(x, (B, 2 * i.K_in, self.L, self.N), "x")
+        if layer.kind == HE_LAYER_CONV:
+            _check_dev(c0, (B, i.K_in, self.L, self.N), "c0", True)
+            _check_dev(sh, (B, i.K_in, self.N), "sh", True)
+        else:
+            _check_dev(c0, (B, self.L, self.N), "c0", True)
+            _check_dev(sh, (B, self.N), "sh", True)
+        _check(load_library().he_layer_inputs_ntt(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(x),
+                                                  _stream(stream)), "he_layer_inputs_ntt")
+        return x
+
+    def layer_from_ntt(self, layer: Layer, x, has_sh: bool, sh_next=None, out=None, stream=None):
+        """MAC, inverse and extraction of `layer` from NTT-domain inputs x (he_conv_layer_ntt /
+        he_fc_layer_ntt)."""
+        import torch
+        B = x.shape[0]
+        i = layer.info
+        _check_dev(x, (B, 2 * i.K_in, self.L, self.N), "x")
+        lib = load_library()
+        if layer.kind == HE_LAYER_CONV:
+            _check_dev(sh_next, (B, i.K_out, self.N), "sh_next", True)
+            shape = (B, i.K_out, self.L, self.N)
+            fn, name = lib.he_conv_layer_ntt, "he_conv_layer_ntt"
+        else:
+            _check_dev(sh_next, (B, i.blocks, i.n_o_p), "sh_next", True)
+            shape = (B, i.blocks, self.L, i.n_o_p)
+            fn, name = lib.he_fc_layer_ntt, "he_fc_layer_ntt"
+        if out is None:
+            out = torch.empty(shape, dtype=torch.int32, device=x.device)
+        _check_dev(out, shape, "out")
+        _check(fn(self.handle, layer.handle, B, _ptr(x), 1 if has_sh else 0, _ptr(sh_next), _ptr(out),
+                  _stream(stream)), name)
         return out
 
     # ---------------------------------------------------------- primitives
