@@ -291,6 +291,81 @@ def paper_protocol_form(he, ctx, st, stream, steps, warmup, sync):
         return time_loop(g.replay, steps, warmup, sync)
 
 
+def resnet50_form(he, args, stream, sync):
+    """ResNet-50-shaped layers (the body after the stem: 52 convs + FC 2048 -> 1000) at
+    N = 16384, 6 limbs.  Each distinct shape is packed, tuned and timed on its own (resident
+    operands of one shape at a time) at batch 1 and batch 16; per-image totals weight each
+    shape by how often the body uses it."""
+    import collections
+    import torch
+    ctx = he.Context(16384, 6, wl.T_PLAIN)
+    N, L, t = 16384, 6, wl.T_PLAIN
+    body = wl.resnet50_body()
+    count = collections.Counter(body)
+    first = {}
+    for k, shp in enumerate(body):
+        first.setdefault(shp, k)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(wl.MASTER_SEED + wl.CONFIG_RESNET50)
+    reps = args.resnet50_reps
+    rows, tot1, tot16, resident = [], 0.0, 0.0, 0
+    for shp, k in sorted(first.items(), key=lambda kv: kv[1]):
+        W = wl.layer_weights(wl.CONFIG_RESNET50, 0, k, shp)
+        if shp.kind == "conv":
+            spec = he.ConvSpec(shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
+            til = ctx.conv_tiling(spec)
+            rho = wl.mask_polys(wl.CONFIG_RESNET50, 0, k, til["K_in"] * shp.c_o, N).reshape(til["K_in"], shp.c_o, N)
+            ly = ctx.pack_conv(spec, W, rho)
+        else:
+            nop = 1 << (shp.n_o - 1).bit_length()
+            if shp.n_i * nop > N:
+                nop = 1 << ((N // shp.n_i).bit_length() - 1)
+            blocks = -(-shp.n_o // nop)
+            rho = wl.mask_polys(wl.CONFIG_RESNET50, 0, k, blocks, N)
+            ly = ctx.pack_fc(he.FCSpec(shp.n_i, shp.n_o), W, rho, wl.layer_bias(wl.CONFIG_RESNET50, 0, k, shp))
+        del rho
+        i = ly.info
+        resident += i.resident_bytes * count[shp]
+        res = {}
+        for B in (1, 16):
+            if shp.kind == "conv":
+                c0 = torch.randint(0, 1 << 29, (B, i.K_in, L, N), generator=gen, device=dev, dtype=torch.int32)
+                sh = torch.randint(0, t, (B, i.K_in, N), generator=gen, device=dev, dtype=torch.int32)
+                shn = torch.randint(0, t, (B, i.K_out, N), generator=gen, device=dev, dtype=torch.int32)
+            else:
+                c0 = torch.randint(0, 1 << 29, (B, L, N), generator=gen, device=dev, dtype=torch.int32)
+                sh = torch.randint(0, t, (B, N), generator=gen, device=dev, dtype=torch.int32)
+                shn = None
+            if not args.no_tune:
+                ctx.autotune(ly, B)
+            seq = he.Sequence(ctx)
+            for _ in range(reps):
+                seq.add(ly, c0, sh, shn)
+            with torch.cuda.stream(stream):
+                T = time_loop(lambda: seq.run(stream), 3, 1, sync)
+            res[B] = T / 3 / reps
+            del seq, c0, sh, shn
+            torch.cuda.empty_cache()
+        tot1 += res[1] * count[shp]
+        tot16 += res[16] * count[shp]
+        rows.append({"layer": k, "shape": f"{shp.c_i}->{shp.c_o} {shp.H}x{shp.W} f{shp.f} s{shp.stride}"
+                     if shp.kind == "conv" else f"fc {shp.n_i}->{shp.n_o}",
+                     "count": count[shp], "slot_stride": int(getattr(i, "s", 0)),
+                     "resident_GB": round(i.resident_bytes / 1e9, 3),
+                     "ms_b1": round(res[1] * 1e3, 4), "ms_per_image_b16": round(res[16] / 16 * 1e3, 4)})
+        log(f"resnet50 {rows[-1]}")
+        ly.free()
+        torch.cuda.empty_cache()
+    n = len(body)
+    return {"layers": n, "distinct_shapes": len(first), "N": N, "limbs": L,
+            "resident_GB_whole_body": round(resident / 1e9, 1),
+            "b1": {"ms_per_image": round(tot1 * 1e3, 3), "layers_per_s": round(n / tot1, 1)},
+            "b16": {"ms_per_image": round(tot16 / 16 * 1e3, 3), "layers_per_s": round(16 * n / tot16, 1)},
+            "per_shape": rows,
+            "note": "synthetic inputs; the 224x224 stem is not included (needs N >= 65536 in this packing)"}
+
+
 # ------------------------------------------------------------------ CPU baseline
 def cpu_baseline(n_layers=3):
     """The oracle's server evaluation of the first layers of the x1 stack on host cores."""
@@ -325,6 +400,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-widths", default="1,2,4", help="plain-20 widths of the batched form")
+    ap.add_argument("--resnet50", action="store_true",
+                    help="also time the ResNet-50-shaped layers (each distinct shape packed in turn, ~2 min)")
+    ap.add_argument("--resnet50-reps", type=int, default=10)
     ap.add_argument("--batched-mac", type=int, default=None,
                     help="pin the MAC variant of the batched form (HE_TUNE_MAC value) instead of tuning it")
     ap.add_argument("--no-served", action="store_true")
@@ -577,6 +655,10 @@ def main():
         result["forms"]["stress"] = stres
         del v4, bufs
         torch.cuda.empty_cache()
+
+    if args.resnet50:
+        log("setup: ResNet-50-shaped layers, N=16384, 6 limbs")
+        result["forms"]["resnet50"] = resnet50_form(he, args, stream, sync)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -111,3 +111,16 @@ __device__ __forceinline__ void mac4(const uint32_t *__restrict__ x, size_t xstr
     r[2] = reduce64(a2, c);
     r[3] = reduce64(a3, c);
 }
+
+// Workgroup ids are dealt to the 8 XCDs round robin.  Remap so that XCD x runs the
+// contiguous logical range [x per, (x + 1) per), per = ceil(total / 8): neighbouring logical
+// workgroups, which write neighbouring words of one line, then share an L2 and their partial
+// writes merge there.  Launch 8 per workgroups; false for the padding ones (the whole
+// workgroup, so it may return before any barrier).
+__device__ __forceinline__ bool xcd_logical(uint32_t w, uint32_t total, uint32_t &logical) {
+    const uint32_t per = (total + 7u) >> 3;
+    logical = (w & 7u) * per + (w >> 3);
+    return logical < total;
+}
+
+inline uint32_t xcd_grid(uint32_t total) { return ((total + 7u) >> 3) << 3; }

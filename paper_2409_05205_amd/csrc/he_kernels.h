@@ -110,8 +110,8 @@ struct MacLdsGeom {
 };
 bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGeom *gm, size_t *lds_bytes);
 hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
-                          uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
-                          hipStream_t st, const LaunchEv *ev = nullptr);
+                          uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool xcd_order,
+                          const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Fused class-form MAC + residue-class tail: one workgroup per output row
 // (b, g, n', l); same output as launch_mac_class followed by launch_tail_rows.

@@ -202,12 +202,15 @@ template <int GS>
 __global__ void __launch_bounds__(ML_THREADS)
 k_mac_lds(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ h, uint32_t B,
           uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s_log, MacLdsGeom gm,
-          LimbConsts lc) {
+          uint32_t xcd_order, LimbConsts lc) {
     extern __shared__ uint32_t lds[];
     // rows padded by two words: 8-byte aligned pairs, and 16 rows of a wave on distinct banks
     const uint32_t TBq = gm.TBq, TNq = gm.TNq, TB = 4 * TBq, TN = 4 * TNq, RP = gm.R + 2, R4 = gm.R >> 2;
     const uint32_t buf_words = (TB + TN) * RP;   // one stage: one input row J, R slots
+    // xcd_order: consecutive tiles and slot ranges on one XCD (see xcd_logical); otherwise the
+    // round-robin dealing of workgroup ids spreads them over the XCDs
     uint32_t w = blockIdx.x;
+    if (xcd_order && !xcd_logical(blockIdx.x, L * gm.ranges * gm.tiles_b * gm.tiles_n, w)) return;
     const uint32_t tb = w % gm.tiles_b;
     w /= gm.tiles_b;
     const uint32_t tn = w % gm.tiles_n;
@@ -592,20 +595,22 @@ bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGe
 }
 
 hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
-                          uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
-                          hipStream_t st, const LaunchEv *ev) {
+                          uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool xcd_order,
+                          const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
     if (B == 0) return hipSuccess;
     MacLdsGeom gm;
     size_t lds = 0;
     if (Juse == 0 || !mac_lds_geometry(B, c_o, N, s, &gm, &lds)) return hipErrorInvalidValue;
     uint32_t s_log = 0;
     while ((1u << s_log) < s) ++s_log;
-    const uint32_t grid = L * gm.ranges * gm.tiles_b * gm.tiles_n;
+    const uint32_t tiles = L * gm.ranges * gm.tiles_b * gm.tiles_n;
+    const uint32_t grid = xcd_order ? xcd_grid(tiles) : tiles;
+    const uint32_t xo = xcd_order ? 1u : 0u;
     switch (gm.GS) {
-        case 2: HE_LAUNCH(ev, k_mac_lds<2>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
-        case 4: HE_LAUNCH(ev, k_mac_lds<4>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
-        case 8: HE_LAUNCH(ev, k_mac_lds<8>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
-        case 16: HE_LAUNCH(ev, k_mac_lds<16>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, lc); break;
+        case 2: HE_LAUNCH(ev, k_mac_lds<2>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, xo, lc); break;
+        case 4: HE_LAUNCH(ev, k_mac_lds<4>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, xo, lc); break;
+        case 8: HE_LAUNCH(ev, k_mac_lds<8>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, xo, lc); break;
+        case 16: HE_LAUNCH(ev, k_mac_lds<16>, dim3(grid), dim3(ML_THREADS), lds, st, X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, xo, lc); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -464,7 +464,7 @@ constexpr int tail_tpw() { return (1 << (LOGM - LOGR)) < 256 ? 256 : (1 << (LOGM
 template <int LOGM, int LOGR>
 __global__ void __launch_bounds__((tail_tpw<LOGM, LOGR>()))
 k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const uint32_t *__restrict__ sh_next,
-            uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, uint32_t RW,
+            uint32_t B, uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, uint32_t RW,
             const uint32_t *__restrict__ twi, const uint32_t *__restrict__ twish, LimbConsts lc) {
     constexpr int M = 1 << LOGM;
     constexpr int T = 1 << (LOGM - LOGR);
@@ -474,7 +474,8 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
     const uint32_t row = tid / T;               // row within the workgroup
     const uint32_t t = tid % T;
     const uint32_t chunks = g_o / RW;
-    uint32_t w = blockIdx.x;
+    uint32_t w;
+    if (!xcd_logical(blockIdx.x, B * K_out * L * chunks, w)) return;
     const uint32_t chunk = w % chunks;
     w /= chunks;
     const uint32_t l = w % L;
@@ -538,10 +539,10 @@ hipError_t tail_launch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next
         constexpr int TPW = tail_tpw<LOGM, LOGR>();
         uint32_t RW = TPW / T;
         if (RW > g_o) RW = g_o;
-        const uint32_t grid = B * K_out * L * (g_o / RW);
+        const uint32_t grid = xcd_grid(B * K_out * L * (g_o / RW));
         const size_t lds = (size_t)(TPW / T) * ((1u << LOGM) + (1u << LOGM >> 5)) * sizeof(uint32_t);
-        HE_LAUNCH(ev, (k_tail_rows<LOGM, LOGR>), dim3(grid), dim3(TPW), lds, st, h, out, sh_next, c_o, g_o, K_out,
-                  L, logN, s_log, RW, twi, twish, lc);
+        HE_LAUNCH(ev, (k_tail_rows<LOGM, LOGR>), dim3(grid), dim3(TPW), lds, st, h, out, sh_next, B, c_o, g_o,
+                  K_out, L, logN, s_log, RW, twi, twish, lc);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;

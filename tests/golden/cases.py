@@ -107,3 +107,22 @@ def batched_layer_inputs(cfg, width, classes, k, B, N, primes):
     sh = wl.share_polys(cfg, 0, width, k, B * g.K_in, N).reshape(B, g.K_in, N)
     shn = wl.share_polys(cfg, 0, width, k, B * g.K_out, N, "shnext").reshape(B, g.K_out, N)
     return {"shape": shp, "geom": g, "F": F, "rho": rho, "c0": c0, "sh": sh, "sh_next": shn}
+
+# ResNet-50-shaped layers at N = 16384, L = 6 (one image): (name, layer index in
+# workloads.resnet50_body()); a 3x3 at 28x28 (s = 16), a 1x1 expansion at 14x14 (s = 64)
+# and a 3x3 at 7x7 (s = 128).
+RESNET_SAMPLES = [("resnet50_l15", 15), ("resnet50_l29", 29), ("resnet50_l47", 47)]
+
+
+def resnet_layer_inputs(k, N, primes):
+    """Server inputs of ResNet-50 body layer k for one image: c0 uniform per limb, shares
+    uniform in [0, t)."""
+    cfg = wl.CONFIG_RESNET50
+    shp = wl.resnet50_body()[k]
+    g = packing.conv_geometry(N, shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
+    F = wl.layer_weights(cfg, 0, k, shp)
+    rho = wl.mask_polys(cfg, 0, k, g.K_in * shp.c_o, N).reshape(g.K_in, shp.c_o, N)
+    c0 = wl.ciphertext_polys(cfg, 0, 0, k, g.K_in, primes, N)
+    sh = wl.share_polys(cfg, 0, 0, k, g.K_in, N)
+    shn = wl.share_polys(cfg, 0, 0, k, g.K_out, N, "shnext")
+    return {"shape": shp, "geom": g, "F": F, "rho": rho, "c0": c0, "sh": sh, "sh_next": shn}

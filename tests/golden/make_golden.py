@@ -115,6 +115,16 @@ def main():
             res["images"][str(b)] = cases.digest(o)
             print(f"{name} image {b} {time.time() - t0:.1f}s", flush=True)
         out["cases"][name] = res
+    ctx = bfv.make_ctx(16384, 6, wl.T_PLAIN)
+    for name, k in cases.RESNET_SAMPLES:
+        t0 = time.time()
+        inp = cases.resnet_layer_inputs(k, 16384, ctx.primes)
+        g = inp["geom"]
+        o = bfv.server_conv(ctx, g, inp["c0"].astype(np.uint64), inp["rho"], packing.pack_conv_filters(inp["F"], g),
+                            inp["sh"], inp["sh_next"])
+        out["cases"][name] = {"config": wl.CONFIG_RESNET50, "N": 16384, "L": 6, "layer": k,
+                              "layers": {str(k): {"kind": "conv", "digest": cases.digest(o), "shape": list(o.shape)}}}
+        print(f"{name} {inp['shape']} {time.time() - t0:.1f}s", flush=True)
     with open(os.path.join(HERE, "server_digests.json"), "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
     print("wrote server_digests.json")

@@ -1,4 +1,5 @@
-"""GPU parity of the LDS-staged batched MAC (HE_TUNE_MAC = 3) against the oracle:
+"""GPU parity of the LDS-staged batched MAC (HE_TUNE_MAC = 3, and 4 with XCD-contiguous
+workgroup order) against the oracle:
 every staging geometry its host planner produces (one or several slot groups
 per block, stages that hold whole blocks or part of one, image and channel tiles
 wider than the batch or the layer), ragged batches and channel counts, with and
@@ -47,10 +48,12 @@ def test_lds_mac_matches_oracle(he, case):
     shn = rng.integers(0, T, (B, g.K_out, N))
     fh = packing.pack_conv_filters(F, g)
     ctx = he.Context(N, L, T)
-    ctx.tune_force(he.HE_TUNE_MAC, 3)
     layer = ctx.pack_conv(he.ConvSpec(c_i, c_o, H, H, 3, stride, 1), F, rho)
     for use_sh in (True, False):
-        got = host(ctx.conv_layer(layer, dev(c0), dev(sh) if use_sh else None, dev(shn)))
-        for b in range(B):
-            want = bfv.server_conv(octx, g, c0[b].astype(np.uint64), rho, fh, sh[b] if use_sh else None, shn[b])
-            assert (got[b] == want).all(), f"image {b} sh={use_sh} s={g.s}"
+        want = [bfv.server_conv(octx, g, c0[b].astype(np.uint64), rho, fh, sh[b] if use_sh else None, shn[b])
+                for b in range(B)]
+        for mac in (3, 4):          # round-robin and XCD-contiguous workgroup order
+            ctx.tune_force(he.HE_TUNE_MAC, mac)
+            got = host(ctx.conv_layer(layer, dev(c0), dev(sh) if use_sh else None, dev(shn)))
+            for b in range(B):
+                assert (got[b] == want[b]).all(), f"mac={mac} image {b} sh={use_sh} s={g.s}"

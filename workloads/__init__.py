@@ -123,6 +123,33 @@ def plain20(width: int = 1, classes: int = 10) -> List[object]:
     return L
 
 
+def resnet50_body(classes: int = 1000) -> List[object]:
+    """The ResNet-50 linear layers after its stem, for a 224x224 input: bottleneck blocks
+    (1x1 reduce, 3x3, 1x1 expand, and a 1x1 projection on the first block of a stage) at
+    56x56 (3 blocks, 64/256 channels), 28x28 (4 blocks, 128/512), 14x14 (6 blocks, 256/1024)
+    and 7x7 (3 blocks, 512/2048), the stride of a stage's first block on its 3x3 and its
+    projection; then global average pooling and FC 2048 -> classes.  52 convs + 1 FC.
+
+    The stem (7x7 stride-2 conv on 224x224, then max pooling) is not included: one
+    zero-padded 230x230 channel needs N >= 65536 coefficients in this packing.
+    """
+    layers: List[object] = []
+    c_in = 64
+    for H_out, mid, out, blocks, stride in ((56, 64, 256, 3, 1), (28, 128, 512, 4, 2), (14, 256, 1024, 6, 2),
+                                           (7, 512, 2048, 3, 2)):
+        for b in range(blocks):
+            st = stride if b == 0 else 1
+            H_in = H_out * st
+            layers.append(ConvShape(c_in, mid, H_in, H_in, f=1, stride=1, pad=0))
+            layers.append(ConvShape(mid, mid, H_in, H_in, f=3, stride=st, pad=1))
+            layers.append(ConvShape(mid, out, H_out, H_out, f=1, stride=1, pad=0))
+            if b == 0:
+                layers.append(ConvShape(c_in, out, H_in, H_in, f=1, stride=st, pad=0))
+            c_in = out
+    layers.append(FCShape(2048, classes))
+    return layers
+
+
 @dataclass(frozen=True)
 class HEParams:
     N: int
@@ -136,6 +163,7 @@ CONFIG_PLAIN20_X1 = 2       # full x1 stack, N=8192, 4 limbs, one image per laun
 CONFIG_BATCHED = 3          # 64 images x widths 1, 2, 4
 CONFIG_SERVED = 4           # Poisson stream of single-layer requests, 128 clients
 CONFIG_STRESS = 5           # x4 / 100 classes, N=16384, 6 limbs, 256 clients
+CONFIG_RESNET50 = 6         # ResNet-50-shaped layers (after the stem), N=16384, 6 limbs
 
 PARAMS_BY_WIDTH = {1: HEParams(8192, 4), 2: HEParams(8192, 4), 4: HEParams(16384, 6)}
 PARAMS_SINGLE = HEParams(4096, 3)
