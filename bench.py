@@ -45,11 +45,11 @@ MAD64_PEAK_G = 22400.0
 PMC_TRAFFIC = {
     # launches carrying the MAC in the plain form: k_mac_tail (conv) and k_mac_full (FC)
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
-            "sha256": "064c6a0f68af9f3f479ce532e260bc7d746bd92091c9c34be62601723d9bf2d3",
-            "bytes_per_launch": 19733467},
+            "sha256": "21d89807abca4b344db469aef0e0d5b436bfc1ed8a85c281ef09fdb674592579",
+            "bytes_per_launch": 19736417},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
-                "sha256": "e80f7ad8bc1bf8e5aef93e5616d40f636d43b86631b0f7b17857bc1916500bf0",
-                "bytes_per_launch": 1826217},
+                "sha256": "9bac2c4eba6c8090cbb07c16ed4bb1cc5bf8bc93a8545a1a90968c5e58ec1352",
+                "bytes_per_launch": 1670553},
 }
 
 
@@ -400,8 +400,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-widths", default="1,2,4", help="plain-20 widths of the batched form")
-    ap.add_argument("--resnet50", action="store_true",
-                    help="also time the ResNet-50-shaped layers (each distinct shape packed in turn, ~2 min)")
+    ap.add_argument("--no-resnet50", action="store_true",
+                    help="skip the ResNet-50-shaped layers (each distinct shape packed and timed in turn)")
     ap.add_argument("--resnet50-reps", type=int, default=10)
     ap.add_argument("--batched-mac", type=int, default=None,
                     help="pin the MAC variant of the batched form (HE_TUNE_MAC value) instead of tuning it")
@@ -656,7 +656,7 @@ def main():
         del v4, bufs
         torch.cuda.empty_cache()
 
-    if args.resnet50:
+    if not args.no_resnet50:
         log("setup: ResNet-50-shaped layers, N=16384, 6 limbs")
         result["forms"]["resnet50"] = resnet50_form(he, args, stream, sync)
 
