@@ -458,6 +458,14 @@ hipError_t inv_launch(const uint32_t *src, uint32_t *dst, const RowMap &map, uin
 // (unscaled Gentleman-Sande, twiddles = the first M entries of the N-point
 // inverse table), then writes the span of residue classes its channels own:
 // out_g[s m + c] for c in [c_lo, c_lo + RW s / g_o), every m < M.
+// A launch has thousands of workgroups, so registers go to occupancy rather than to
+// prefetched twiddles (each pass reads its own from cache), and the sh' words of the
+// write are fetched with the channel rows, so that their latency overlaps the inverse.
+//
+// PassTw sizes its prefetch for the workgroup size it is given: at 2048 threads the
+// register budget leaves nothing to prefetch for radix 8 and up.
+constexpr int TW_IN_PASS = 2048;
+
 template <int LOGM, int LOGR>
 constexpr int tail_tpw() { return (1 << (LOGM - LOGR)) < 256 ? 256 : (1 << (LOGM - LOGR)); }
 
@@ -491,8 +499,14 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
     const bool exists = active && n < c_o;
     const uint32_t *W = twi + (size_t)l * N;
     const uint32_t *Wsh = twish + (size_t)l * N;
-    PassTw<LOGM, LOGR, tail_tpw<LOGM, LOGR>()> ptw;
-    inv_tw_load<LOGM, LOGR, tail_tpw<LOGM, LOGR>(), 0>(ptw, t, W, Wsh);
+    PassTw<LOGM, LOGR, TW_IN_PASS> ptw;
+    inv_tw_load<LOGM, LOGR, TW_IN_PASS, 0>(ptw, t, W, Wsh);
+    // g_o, RW and s are powers of two: class width, span and indices by shifts
+    const uint32_t cw_log = s_log - (31u - __clz(g_o));
+    const uint32_t span_log = (31u - __clz(RW)) + cw_log;
+    const uint32_t c_lo = np0 << cw_log;
+    const uint32_t *sh = sh_next ? sh_next + (size_t)(b * K_out + g) * N : nullptr;
+    const uint32_t total = (uint32_t)M << span_log;
     if (active) {
         const uint32_t *src = h + ((size_t)(b * c_o + (exists ? n : 0)) * L + l) * M;
 #pragma unroll
@@ -501,32 +515,41 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
             my[lpad(idx)] = exists ? src[idx] : 0u;
         }
     }
+    // the sh' words of the first 16 write rounds, fetched now so that they arrive during the inverse
+    constexpr int TPF = 16;
+    uint32_t shv[TPF];
+#pragma unroll
+    for (int i = 0; i < TPF; ++i) {
+        const uint32_t e = tid + i * blockDim.x;
+        shv[i] = (sh && e < total) ? sh[((e >> span_log) << s_log) + c_lo + (e & ((1u << span_log) - 1u))] : 0u;
+    }
     __syncthreads();
     uint32_t v[1 << LOGR];
-    inv_pass<LOGM, LOGR, tail_tpw<LOGM, LOGR>(), 0>(v, ptw, my, t, W, Wsh, c.q, c.q2);
+    inv_pass<LOGM, LOGR, TW_IN_PASS, 0>(v, ptw, my, t, W, Wsh, c.q, c.q2);
     __syncthreads();
     if (active) {
 #pragma unroll
         for (int i = 0; i < (1 << LOGR); ++i) my[lpad(inv_final_idx<LOGM, LOGR>(t, i))] = csub(v[i], c.q);
     }
     __syncthreads();
-    // g_o, RW and s are powers of two: class width, span and indices by shifts
-    const uint32_t cw_log = s_log - (31u - __clz(g_o));
-    const uint32_t span_log = (31u - __clz(RW)) + cw_log;
-    const uint32_t c_lo = np0 << cw_log;
     uint32_t *o = out + ((size_t)(b * K_out + g) * L + l) * N;
-    const uint32_t *sh = sh_next ? sh_next + (size_t)(b * K_out + g) * N : nullptr;
-    const uint32_t total = (uint32_t)M << span_log;
-#pragma unroll 4
-    for (uint32_t e = tid; e < total; e += blockDim.x) {
+    auto put = [&](uint32_t e, uint32_t shw) {
         const uint32_t m = e >> span_log;
         const uint32_t off = e & ((1u << span_log) - 1u);
         const uint32_t r = off >> cw_log;
         uint32_t val = 0;
         if ((off & ((1u << cw_log) - 1u)) == 0 && g * g_o + np0 + r < c_o) val = lds[r * MP + lpad(m)];
-        const uint32_t k = (m << s_log) + c_lo + off;
-        if (sh) val = csub(val + mul_delta_msg(sh[k], c), c.q);
-        o[k] = val;
+        if (sh) val = csub(val + mul_delta_msg(shw, c), c.q);
+        o[(m << s_log) + c_lo + off] = val;
+    };
+#pragma unroll
+    for (int i = 0; i < TPF; ++i) {
+        const uint32_t e = tid + i * blockDim.x;
+        if (e < total) put(e, shv[i]);
+    }
+    for (uint32_t e = tid + TPF * blockDim.x; e < total; e += blockDim.x) {
+        const uint32_t m = e >> span_log, off = e & ((1u << span_log) - 1u);
+        put(e, sh ? sh[(m << s_log) + c_lo + off] : 0u);
     }
 }
 
