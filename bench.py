@@ -45,11 +45,11 @@ MAD64_PEAK_G = 22400.0
 PMC_TRAFFIC = {
     # launches carrying the MAC in the plain form: k_mac_tail (conv) and k_mac_full (FC)
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
-            "sha256": "21d89807abca4b344db469aef0e0d5b436bfc1ed8a85c281ef09fdb674592579",
-            "bytes_per_launch": 19736417},
+            "sha256": "2c13c2fded04c042433b6c80644e2c4efe98772c2a25be2812e08ebec736232a",
+            "bytes_per_launch": 19733496},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
-                "sha256": "9bac2c4eba6c8090cbb07c16ed4bb1cc5bf8bc93a8545a1a90968c5e58ec1352",
-                "bytes_per_launch": 1670553},
+                "sha256": "e56a1d7b471c9453f5c4c2cc30d512b0191b87ed8d0f512b7afa97396981edd2",
+                "bytes_per_launch": 1670566},
 }
 
 
