@@ -47,6 +47,12 @@ struct PassTw {
     uint32_t w[TOTAL], ws[TOTAL];
 };
 
+// PassTw sizes its prefetch for the workgroup size it is given.  At this size the register
+// budget leaves nothing to prefetch for radix 8 and up: each pass then reads its twiddles from
+// cache, which keeps registers for occupancy in launches of many rows.
+constexpr int TW_IN_PASS = 2048;
+
+
 // Forward pass P, stage k, group g: the pair (vv, vv + half) uses twiddle
 // psi^brv(2^(S0+k) + ((F >> LO) << k) + (vv >> (RP - k))), slot (2^k - 1) + (vv >> (RP - k)).
 template <int LOGN, int LOGR, int TPB, int P>
@@ -177,11 +183,14 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], const PassTw<
     if constexpr (S0 + RP < LOGN) fwd_pass<LOGN, LOGR, TPB, P + 1>(v, tw, lds, tid, in, W, Wsh, q, q2);
 }
 
-template <int LOGN, int LOGR>
+// PF: twiddles of the first passes prefetched into registers (a launch of a few rows, where
+// their latency would otherwise stand alone) or read per pass (many rows: occupancy instead).
+template <int LOGN, int LOGR, bool PF>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 k_ntt_fwd(FwdJobs jobs, const uint32_t *__restrict__ tw, const uint32_t *__restrict__ twsh, LimbConsts lc) {
     constexpr int N = 1 << LOGN;
     constexpr int T = 1 << (LOGN - LOGR);
+    constexpr int TWB = PF ? T : TW_IN_PASS;
     __shared__ uint32_t lds[N + (N >> 5)];
     const uint32_t tid = threadIdx.x;
     uint32_t r = blockIdx.x;
@@ -197,10 +206,10 @@ k_ntt_fwd(FwdJobs jobs, const uint32_t *__restrict__ tw, const uint32_t *__restr
     const uint32_t q = lc.l[l].q, q2 = lc.l[l].q2;
     const uint32_t *W = tw + (size_t)l * N;
     const uint32_t *Wsh = twsh + (size_t)l * N;
-    PassTw<LOGN, LOGR, T> ptw;
-    fwd_tw_load<LOGN, LOGR, T, 0>(ptw, tid, W, Wsh);
+    PassTw<LOGN, LOGR, TWB> ptw;
+    fwd_tw_load<LOGN, LOGR, TWB, 0>(ptw, tid, W, Wsh);
     uint32_t v[1 << LOGR];
-    fwd_pass<LOGN, LOGR, T, 0>(v, ptw, lds, tid, in, W, Wsh, q, q2);
+    fwd_pass<LOGN, LOGR, TWB, 0>(v, ptw, lds, tid, in, W, Wsh, q, q2);
 #pragma unroll
     for (int i = 0; i < (1 << LOGR); ++i) {
         const uint32_t idx = tid + i * T;
@@ -423,7 +432,11 @@ template <int LOGN, int LOGR>
 hipError_t fwd_launch(const FwdJobs &jobs, uint32_t rows, const uint32_t *tw, const uint32_t *twsh,
                       const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
     if constexpr (valid_variant(LOGN, LOGR)) {
-        HE_LAUNCH(ev, (k_ntt_fwd<LOGN, LOGR>), dim3(rows), dim3(1 << (LOGN - LOGR)), 0, st, jobs, tw, twsh, lc);
+        // a launch of up to one row per CU keeps the twiddle prefetch; larger ones read per pass
+        if (rows <= 256)
+            HE_LAUNCH(ev, (k_ntt_fwd<LOGN, LOGR, true>), dim3(rows), dim3(1 << (LOGN - LOGR)), 0, st, jobs, tw, twsh, lc);
+        else
+            HE_LAUNCH(ev, (k_ntt_fwd<LOGN, LOGR, false>), dim3(rows), dim3(1 << (LOGN - LOGR)), 0, st, jobs, tw, twsh, lc);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -461,10 +474,6 @@ hipError_t inv_launch(const uint32_t *src, uint32_t *dst, const RowMap &map, uin
 // A launch has thousands of workgroups, so registers go to occupancy rather than to
 // prefetched twiddles (each pass reads its own from cache), and the sh' words of the
 // write are fetched with the channel rows, so that their latency overlaps the inverse.
-//
-// PassTw sizes its prefetch for the workgroup size it is given: at 2048 threads the
-// register budget leaves nothing to prefetch for radix 8 and up.
-constexpr int TW_IN_PASS = 2048;
 
 template <int LOGM, int LOGR>
 constexpr int tail_tpw() { return (1 << (LOGM - LOGR)) < 256 ? 256 : (1 << (LOGM - LOGR)); }
