@@ -45,11 +45,11 @@ MAD64_PEAK_G = 22400.0
 PMC_TRAFFIC = {
     # launches carrying the MAC in the plain form: k_mac_tail (conv) and k_mac_full (FC)
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
-            "sha256": "2c13c2fded04c042433b6c80644e2c4efe98772c2a25be2812e08ebec736232a",
-            "bytes_per_launch": 19733496},
+            "sha256": "57576fb8a95a351948f93c89204c364ee9429c1ec8c82ebe33517eb2defea735",
+            "bytes_per_launch": 19733585},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
-                "sha256": "e56a1d7b471c9453f5c4c2cc30d512b0191b87ed8d0f512b7afa97396981edd2",
-                "bytes_per_launch": 1670566},
+                "sha256": "668992c31db973b91bbbf9ed5279e55ca76ceb0aee6a5ca3324c965f38cbb66d",
+                "bytes_per_launch": 1670537},
 }
 
 
