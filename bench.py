@@ -45,11 +45,11 @@ MAD64_PEAK_G = 22400.0
 PMC_TRAFFIC = {
     # launches carrying the MAC in the plain form: k_mac_tail (conv) and k_mac_full (FC)
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
-            "sha256": "57576fb8a95a351948f93c89204c364ee9429c1ec8c82ebe33517eb2defea735",
-            "bytes_per_launch": 19733585},
+            "sha256": "6e7d196d478803f41a9983f30101622d76676ebd8900e8ef124f8f0311c25b3d",
+            "bytes_per_launch": 19734717},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
                 "sha256": "668992c31db973b91bbbf9ed5279e55ca76ceb0aee6a5ca3324c965f38cbb66d",
-                "bytes_per_launch": 1670537},
+                "bytes_per_launch": 1670603},
 }
 
 

@@ -327,8 +327,9 @@ void he_server_free(he_server *srv);
  * 1 (register-blocked batched MAC), 2 (residue-class conv layers: MAC, inverse
  * and extraction fused, one workgroup per output row), 3 (residue-class conv
  * layers, B >= 2: LDS-staged batched MAC over image x channel tiles), 4 (as
- * 3, with neighbouring tiles on one XCD) or -1
- * (automatic: 2 at B = 1; at B >= 4, 3 for residue-class layers and 1 for
+ * 3, with neighbouring tiles on one XCD), 5 and 6 (as 3 and 4, each stage
+ * moved from memory to LDS by DMA, three stages in flight) or -1
+ * (automatic: 2 at B = 1; at B >= 4, 5 for residue-class layers and 1 for
  * full-length ones); a value the layer's shape does not allow falls back to 0.  Every value yields the same output words.  he_tune_force pins a knob for the whole context (tests
  * sweep all values with it).  he_autotune_layer tunes the knobs of one layer at
  * batch B one after another: each candidate is timed as a whole layer call on

@@ -190,10 +190,11 @@ int knob(he_ctx *ctx, int which, uint32_t logsize, uint32_t rows) {
 }
 
 // Conv MAC variant of a layer at batch B: 0 streaming (then tail), 1 register-blocked
-// batched (then tail), 2 fused MAC + residue-class tail, 3 LDS-staged batched (then
-// tail), 4 as 3 with XCD-contiguous workgroup order.  A tuned or forced value is used when the layer's shape allows it; otherwise,
-// and by default, B = 1 takes the fused form and B >= 4 a batched one (3 for the
-// residue-class form, 1 for the full-length form).
+// batched (then tail), 2 fused MAC + residue-class tail, 3 LDS-staged batched (then tail),
+// 4 as 3 with XCD-contiguous workgroup order, 5 and 6 as 3 and 4 with the stages moved to LDS
+// by DMA.  A tuned or forced value is used when the layer's shape allows it; otherwise, and by
+// default, B = 1 takes the fused form and B >= 4 a batched one (5 for the residue-class form,
+// 1 for the full-length form).
 bool mac_tiled_ok(const he_layer *ly, uint32_t B) {
     const he_layer_info &in = ly->info;
     const bool cls = in.flags == HE_PACK_CLASS_INTT;
@@ -214,12 +215,12 @@ bool mac_lds_ok(const he_layer *ly, uint32_t B) {
 int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
     const int mk = knob(ctx, HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B);
     const bool tiled_ok = mac_tiled_ok(ly, B), fused_ok = mac_fused_ok(ctx, ly);
-    if (mk == 3 || mk == 4) return mac_lds_ok(ly, B) ? mk : 0;
+    if (mk == 3 || mk == 4 || mk == 5 || mk == 6) return mac_lds_ok(ly, B) ? mk : 0;
     if (mk == 2) return fused_ok ? 2 : 0;
     if (mk == 1) return tiled_ok ? 1 : 0;
     if (mk == 0) return 0;
     if (B == 1 && fused_ok) return 2;
-    if (B >= 4 && mac_lds_ok(ly, B)) return 3;
+    if (B >= 4 && mac_lds_ok(ly, B)) return 5;
     return tiled_ok && B >= 4 ? 1 : 0;
 }
 
@@ -478,10 +479,8 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         std::vector<int> macs{0};
         if (mac_tiled_ok(ly, B)) macs.push_back(1);
         if (mac_fused_ok(ctx, ly)) macs.push_back(2);
-        if (mac_lds_ok(ly, B)) {
-            macs.push_back(3);
-            macs.push_back(4);
-        }
+        if (mac_lds_ok(ly, B))
+            for (int m : {3, 4, 5, 6}) macs.push_back(m);
         if (B == 1) macs.clear();
         if (rc == HE_OK && macs.size() > 1) rc = pick(HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B, macs, true);
         const uint32_t logm = logN - log2u(in.s);
@@ -1039,6 +1038,8 @@ int conv_from_x(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *xn,
         ProfScope ps(ctx, HE_K_MAC);
         if (mk == 3 || mk == 4)
             e = launch_mac_lds(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, mk == 4, ctx->lc, st, ps.ev());
+        else if (mk == 5 || mk == 6)
+            e = launch_mac_dma(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, mk == 6, ctx->lc, st, ps.ev());
         else if (tiled)
             e = launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, cls, ctx->lc, st, ps.ev());
         else if (cls)

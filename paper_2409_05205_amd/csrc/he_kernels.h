@@ -112,6 +112,11 @@ bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGe
 hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
                           uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool xcd_order,
                           const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
+// Same products and output as launch_mac_lds, with the stages moved to LDS by global_load_lds
+// (three stage buffers, no register staging).
+hipError_t launch_mac_dma(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
+                          uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool xcd_order,
+                          const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Fused class-form MAC + residue-class tail: one workgroup per output row
 // (b, g, n', l); same output as launch_mac_class followed by launch_tail_rows.
