@@ -169,6 +169,35 @@ class Stack:
                 tot += B * c_o * L * out_per * 4
         return tot
 
+    def fwd_bytes(self):
+        """Algorithmic HBM bytes of one pass's forward transforms: each c0 row read and written per
+        limb; each sh row read once and written for every limb."""
+        L, N = self.ctx.L, self.ctx.N
+        tot = 0
+        for ly, B, c0, sh, shn in self.steps:
+            rows = B * ly.info.K_in
+            tot += rows * L * N * 8
+            if sh is not None:
+                tot += rows * N * 4 + rows * L * N * 4
+        return tot
+
+    def inverse_bytes(self):
+        """Algorithmic HBM bytes of one pass's inverse launches: the MAC output read (block sums
+        of every channel, or full rows for FC and full-form conv), sh' read once per output
+        polynomial, the output polynomials (FC: their n_o' kept coefficients) written."""
+        L, N = self.ctx.L, self.ctx.N
+        tot = 0
+        for (ly, B, c0, sh, shn), rows in zip(self.steps, self.rows):
+            i = ly.info
+            if ly.kind == 0:
+                per = N // i.s if i.flags == 0 else N
+                tot += B * rows * L * per * 4 + B * i.K_out * L * N * 4
+                tot += B * i.K_out * N * 4 if shn is not None else 0
+            else:
+                tot += B * rows * L * N * 4 + B * rows * L * i.n_o_p * 4
+                tot += B * rows * i.n_o_p * 4 if shn is not None else 0
+        return tot
+
     def butterflies_fwd(self):
         """Forward-NTT butterflies of one pass (c0 rows, plus sh rows where present)."""
         L, N = self.ctx.L, self.ctx.N
@@ -217,10 +246,11 @@ def percentile(xs, p):
     return xs[k]
 
 
-def batched_rooflines(he, ctx, st, stream, sync, passes=2):
+def batched_rooflines(he, ctx, st, stream, sync, passes=2, plan=None):
     """Per-kind kernel time of eager passes over a batched stack (HIP events on the launch
     stream), against the integer roofs: forward and inverse butterflies against the measured
-    butterfly rate, MAC products against the 64-bit multiply-add rate."""
+    butterfly rate, MAC products against the 64-bit multiply-add rate.  Each kind also gets its
+    algorithmic HBM bytes per pass over its time as a fraction of HBM (`hbm_frac`)."""
     import torch
     kinds = [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL), ("intt", he.HE_K_INTT),
              ("mac_tail", he.HE_K_MAC_TAIL)]
@@ -238,17 +268,25 @@ def batched_rooflines(he, ctx, st, stream, sync, passes=2):
     ctx.profile_reset()
     out = {}
     fwd_rate = st.butterflies_fwd() / (ms["ntt_fwd"] / 1e3) / 1e9 if ms["ntt_fwd"] else None
+    def hbm(nbytes, t_ms):
+        gbs = nbytes / (t_ms / 1e3) / 1e9
+        return {"hbm_bytes_per_batch": int(nbytes), "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
     out["ntt_fwd"] = {"ms_per_batch": round(ms["ntt_fwd"], 3), "bound": "alu", "achieved": round(fwd_rate, 1),
-                      "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(fwd_rate / BFLY_PEAK_G, 4)}
+                      "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(fwd_rate / BFLY_PEAK_G, 4),
+                      **hbm(st.fwd_bytes(), ms["ntt_fwd"])}
     mac_ms = ms["mac"] + ms["mac_tail"]
     mac_rate = st.modmuls() / (mac_ms / 1e3) / 1e9
     out["mac"] = {"ms_per_batch": round(mac_ms, 3), "bound": "alu", "achieved": round(mac_rate, 1),
                   "peak": MAD64_PEAK_G, "unit": "Gmodmul/s", "frac": round(mac_rate / MAD64_PEAK_G, 4)}
+    if plan is not None:
+        out["mac"].update(hbm(st.mac_kernel_bytes(plan), mac_ms))
     inv_ms = ms["tail"] + ms["intt"]
     if inv_ms:
         inv_rate = st.tail_butterflies() / (inv_ms / 1e3) / 1e9
         out["inverse"] = {"ms_per_batch": round(inv_ms, 3), "bound": "alu", "achieved": round(inv_rate, 1),
-                          "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(inv_rate / BFLY_PEAK_G, 4)}
+                          "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(inv_rate / BFLY_PEAK_G, 4),
+                          **hbm(st.inverse_bytes(), inv_ms)}
     return out
 
 
@@ -612,7 +650,8 @@ def main():
                                  "ms_per_batch": round(T / args.batched_steps * 1e3, 3),
                                  "image_layers_per_batch": il,
                                  "limb_poly_macs_per_s": round(bst.modmuls() / N * args.batched_steps / T, 1),
-                                 "kernel_rooflines": batched_rooflines(he, bctx, bst, stream, sync)}
+                                 "kernel_rooflines": batched_rooflines(he, bctx, bst, stream, sync,
+                                                                       plan=bst.mac_plan(he))}
             log(f"batched x{width}: {json.dumps(bres[f'x{width}'])}")
             tot_layers += il * args.batched_steps
             tot_time += T
