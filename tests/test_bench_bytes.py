@@ -1,0 +1,57 @@
+"""The algorithmic byte and operation counts bench.py divides by measured times, checked against
+hand counts of one residue-class conv layer and one FC layer (no GPU: the counts read only
+layer geometry)."""
+import bench
+
+
+class _Info:
+    def __init__(self, **k):
+        self.__dict__.update(k)
+
+
+class _Layer:
+    def __init__(self, kind, info):
+        self.kind = kind
+        self.info = info
+
+
+class _Ctx:
+    L = 4
+    N = 8192
+
+
+def _stack():
+    st = bench.Stack.__new__(bench.Stack)
+    st.ctx = _Ctx()
+    share = object()   # any non-None tensor stands for a present share
+    # conv 16 -> 16 at 32 x 32 (s = 4, K_in = K_out = 4), 64 images, with sh and sh'; FC block of
+    # n_o' = 16 rows, 32 inputs, with sh and without sh'
+    st.steps = [(_Layer(0, _Info(K_in=4, K_out=4, s=4, flags=0, n_o_p=0)), 64, None, share, share),
+                (_Layer(1, _Info(K_in=1, K_out=0, s=0, flags=0, n_o_p=16)), 32, None, share, None)]
+    st.rows = [16, 1]
+    return st
+
+
+def test_forward_bytes():
+    L, N = 4, 8192
+    conv = 64 * 4 * L * N * 8 + 64 * 4 * N * 4 + 64 * 4 * L * N * 4    # c0 rows r+w; sh read once, written per limb
+    fc = 32 * L * N * 8 + 32 * N * 4 + 32 * L * N * 4
+    assert _stack().fwd_bytes() == conv + fc
+
+
+def test_inverse_bytes():
+    L, N, M = 4, 8192, 8192 // 4
+    conv = 64 * 16 * L * M * 4 + 64 * 4 * L * N * 4 + 64 * 4 * N * 4     # block sums, out, sh'
+    fc = 32 * 1 * L * N * 4 + 32 * 1 * L * 16 * 4                        # MAC rows in, n_o' out
+    assert _stack().inverse_bytes() == conv + fc
+
+
+def test_mac_bytes_and_counts():
+    L, N, M = 4, 8192, 8192 // 4
+    st = _stack()
+    conv = 8 * 16 * L * N * 4 + 64 * 8 * L * N * 4 + 64 * 16 * L * M * 4   # operands, inputs, block sums
+    fc = 2 * 1 * L * N * 4 + 32 * 2 * L * N * 4 + 32 * 1 * L * N * 4
+    assert st.mac_kernel_bytes(["split", "split"]) == conv + fc
+    assert st.modmuls() == 64 * 8 * 16 * L * N + 32 * 2 * 1 * L * N
+    assert st.butterflies_fwd() == (64 * 4 * L * 2 + 32 * L * 2) * (N // 2) * 13
+    assert st.tail_butterflies() == 64 * 16 * L * (M // 2) * 11 + 32 * 1 * L * (N // 2) * 13
