@@ -45,11 +45,11 @@ MAD64_PEAK_G = 22400.0
 PMC_TRAFFIC = {
     # launches carrying the MAC in the plain form: k_mac_tail (conv) and k_mac_full (FC)
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
-            "sha256": "6e7d196d478803f41a9983f30101622d76676ebd8900e8ef124f8f0311c25b3d",
-            "bytes_per_launch": 19734717},
+            "sha256": "2bd42d1e0799a5871a2b67403a1f4eb16f61c113b5281ab2d9cce526722071d7",
+            "bytes_per_launch": 19734704},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
                 "sha256": "668992c31db973b91bbbf9ed5279e55ca76ceb0aee6a5ca3324c965f38cbb66d",
-                "bytes_per_launch": 1670603},
+                "bytes_per_launch": 1670582},
 }
 
 

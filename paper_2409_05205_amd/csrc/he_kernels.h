@@ -108,7 +108,9 @@ struct MacLdsGeom {
     uint32_t ranges;          // slot ranges per limb
     uint32_t tiles_b, tiles_n;
 };
-bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGeom *gm, size_t *lds_bytes);
+// short_stage: slots per stage for blocks shorter than 16 slots (32 with register staging, 64 by DMA).
+bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGeom *gm, size_t *lds_bytes,
+                      uint32_t short_stage);
 hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
                           uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool xcd_order,
                           const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);

@@ -374,7 +374,8 @@ k_mac_dma(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint3
     extern __shared__ uint32_t lds[];
     const uint32_t TBq = gm.TBq, TNq = gm.TNq, TB = 4 * TBq, TN = 4 * TNq, R = gm.R;
     const uint32_t R4 = R >> 2, r4_log = 31u - __clz(R4);
-    // rows whose starts share a bank: R words apart, 32 banks; they get distinct chunk permutations
+    // rows whose starts share a bank (R words apart, 32 banks) get distinct chunk permutations;
+    // at R >= 32 every row starts on bank 0 and the low row bits spread 8 rows over the banks
     const uint32_t sw_shift = R >= 32 ? 0u : 5u - (31u - __clz(R));
     const uint32_t buf_words = (TB + TN) * R;
     uint32_t w = blockIdx.x;
@@ -714,7 +715,8 @@ hipError_t launch_mac_tiled(const uint32_t *X, const uint32_t *Op, uint32_t *out
     return hipGetLastError();
 }
 
-bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGeom *gm, size_t *lds_bytes) {
+bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGeom *gm, size_t *lds_bytes,
+                      uint32_t short_stage) {
     if (B == 0 || c_o == 0 || s < 2 || s > N || N < 256) return false;
     auto pow2_at_least = [](uint32_t x) {
         uint32_t p = 1;
@@ -735,9 +737,9 @@ bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGe
         if (TNq >= TBq && TNq > 1) TNq >>= 1;
         else TBq >>= 1;
     }
-    // blocks shorter than 16 slots: stage 32 slots (rows of 128 contiguous bytes), trading
-    // image x channel reuse for full-line loads
-    while (GS < 16 && (ML_THREADS / (TBq * TNq)) * GS < 32 && TBq * TNq > 1) {
+    // blocks shorter than 16 slots: stage short_stage slots (rows of 128 or 256 contiguous
+    // bytes), trading image x channel reuse for full-line loads and more products per stage
+    while (GS < 16 && (ML_THREADS / (TBq * TNq)) * GS < short_stage && TBq * TNq > 1) {
         if (TBq >= TNq) TBq >>= 1;
         else TNq >>= 1;
     }
@@ -770,7 +772,7 @@ hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, ui
     if (B == 0) return hipSuccess;
     MacLdsGeom gm;
     size_t lds = 0;
-    if (Juse == 0 || !mac_lds_geometry(B, c_o, N, s, &gm, &lds)) return hipErrorInvalidValue;
+    if (Juse == 0 || !mac_lds_geometry(B, c_o, N, s, &gm, &lds, 32)) return hipErrorInvalidValue;
     uint32_t s_log = 0;
     while ((1u << s_log) < s) ++s_log;
     const uint32_t tiles = L * gm.ranges * gm.tiles_b * gm.tiles_n;
@@ -792,9 +794,10 @@ hipError_t launch_mac_dma(const uint32_t *X, const uint32_t *Op, uint32_t *h, ui
     if (B == 0) return hipSuccess;
     MacLdsGeom gm;
     size_t lds_pad = 0;
-    if (Juse == 0 || !mac_lds_geometry(B, c_o, N, s, &gm, &lds_pad)) return hipErrorInvalidValue;
-    // 16-byte chunks: R a power of two in [4, 32]; every slot of a stage within ML_UNITS loads per thread
-    if (gm.R < 4 || gm.R > 32 || (gm.R & (gm.R - 1)) || (4 * (gm.TBq + gm.TNq)) * (gm.R / 4) > ML_UNITS * ML_THREADS)
+    // without register staging, blocks shorter than 16 slots take 64-slot stages (x4 MAC 10.3 -> 9.4 ms)
+    if (Juse == 0 || !mac_lds_geometry(B, c_o, N, s, &gm, &lds_pad, 64)) return hipErrorInvalidValue;
+    // 16-byte chunks: R a power of two in [4, 64]; every slot of a stage within ML_UNITS loads per thread
+    if (gm.R < 4 || gm.R > 64 || (gm.R & (gm.R - 1)) || (4 * (gm.TBq + gm.TNq)) * (gm.R / 4) > ML_UNITS * ML_THREADS)
         return hipErrorInvalidValue;
     const size_t stage = (size_t)MD_BUFS * 4 * (gm.TBq + gm.TNq) * gm.R;
     const size_t red = (size_t)ML_THREADS * ML_RED_STRIDE;
