@@ -44,20 +44,25 @@ MAD64_PEAK_G = 22400.0
 # copy), valid while the kernel source is the one that was measured.
 PMC_TRAFFIC = {
     # launches carrying the MAC in the plain form: k_mac_tail (conv) and k_mac_full (FC)
+    # (plan: the MAC form of each of the 20 layers in the measured run, F fused, S split)
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
+            "plan": "FSSSSSSFFFFFFFFFFFFS",
             "sha256": "2bd42d1e0799a5871a2b67403a1f4eb16f61c113b5281ab2d9cce526722071d7",
-            "bytes_per_launch": 19734704},
+            "bytes_per_launch": 18879312},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
                 "sha256": "668992c31db973b91bbbf9ed5279e55ca76ceb0aee6a5ca3324c965f38cbb66d",
-                "bytes_per_launch": 1670582},
+                "bytes_per_launch": 1670517},
 }
 
 
-def pmc_traffic(kind):
-    """Counter-measured HBM bytes per launch, or None once a measured source has changed."""
+def pmc_traffic(kind, plan=None):
+    """Counter-measured HBM bytes per launch, or None once a measured source has changed or the
+    layers' MAC forms (one letter per layer: F fused, S split) differ from the measured run's."""
     import hashlib
     rec = PMC_TRAFFIC.get(kind)
     if rec is None:
+        return None
+    if plan is not None and rec.get("plan") not in (None, plan):
         return None
     h = hashlib.sha256()
     for src in rec["sources"]:
@@ -567,9 +572,10 @@ def main():
     mac_avg_s = mac_ms / 1e3 / mac_n
     achieved = mac_bytes / mac_launches_per_step / mac_avg_s / 1e9
     n_fused = plan.count("fused")
+    plan_letters = "".join("F" if p == "fused" else "S" for p in plan)
     roof_mac = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": pmc_traffic("mac") if n_fused == n_layers - 1 else None,
+                "traffic": pmc_traffic("mac", plan_letters), "mac_forms": plan_letters,
                 "algorithmic_bytes_per_launch": mac_bytes // mac_launches_per_step,
                 "kernel": f"k_mac_tail (fused MAC + residue-class inverse, {n_fused} layers) / "
                           f"k_mac_class, k_mac_full (split MAC, {n_layers - n_fused} layers)",

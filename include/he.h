@@ -329,13 +329,14 @@ void he_server_free(he_server *srv);
  * layers, B >= 2: LDS-staged batched MAC over image x channel tiles), 4 (as
  * 3, with neighbouring tiles on one XCD), 5 and 6 (as 3 and 4, each stage
  * moved from memory to LDS by DMA, three stages in flight) or -1
- * (automatic: 2 at B = 1; at B >= 4, 5 for residue-class layers and 1 for
+ * (automatic: 2 at B = 1, except 0 for layers with K_in >= 2 and at most 64
+ * output rows K_out g_o L; at B >= 4, 5 for residue-class layers and 1 for
  * full-length ones); a value the layer's shape does not allow falls back to 0.  Every value yields the same output words.  he_tune_force pins a knob for the whole context (tests
  * sweep all values with it).  he_autotune_layer tunes the knobs of one layer at
  * batch B one after another: each candidate is timed as a whole layer call on
  * scratch buffers (median of 5, caches evicted before each), and the fastest is
- * kept for later calls with that shape (at B = 1 the MAC form is not tuned: the
- * fused launch is kept).  It allocates and frees its scratch
+ * kept for later calls with that shape (at B = 1 the MAC form leaves the automatic
+ * rule above only for a form at least 5 % faster).  It allocates and frees its scratch
  * (about 512 MiB plus one call's buffers) and synchronises the stream.
  * he_tune_get reads a kept choice back (key: knob, log2 of the transform size,
  * rows per launch; for HE_TUNE_MAC the layer and B).

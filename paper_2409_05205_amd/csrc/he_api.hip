@@ -193,8 +193,9 @@ int knob(he_ctx *ctx, int which, uint32_t logsize, uint32_t rows) {
 // batched (then tail), 2 fused MAC + residue-class tail, 3 LDS-staged batched (then tail),
 // 4 as 3 with XCD-contiguous workgroup order, 5 and 6 as 3 and 4 with the stages moved to LDS
 // by DMA.  A tuned or forced value is used when the layer's shape allows it; otherwise, and by
-// default, B = 1 takes the fused form and B >= 4 a batched one (5 for the residue-class form,
-// 1 for the full-length form).
+// default, B = 1 takes the fused form (the streaming one for layers with K_in >= 2 and at most
+// 64 output rows) and B >= 4 a batched one (5 for the residue-class form, 1 for the
+// full-length form).
 bool mac_tiled_ok(const he_layer *ly, uint32_t B) {
     const he_layer_info &in = ly->info;
     const bool cls = in.flags == HE_PACK_CLASS_INTT;
@@ -219,7 +220,13 @@ int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
     if (mk == 2) return fused_ok ? 2 : 0;
     if (mk == 1) return tiled_ok ? 1 : 0;
     if (mk == 0) return 0;
-    if (B == 1 && fused_ok) return 2;
+    if (B == 1 && fused_ok) {
+        // a layer with several input polys and output rows for at most a quarter of the CUs
+        // streams its MAC over many workgroups faster than the fused launch's few, even with
+        // the tail as a second launch (what the autotuner picks for such layers)
+        const he_layer_info &in = ly->info;
+        return (in.K_in >= 2 && 4 * in.K_out * in.g_o * in.L <= 256) ? 0 : 2;
+    }
     if (B >= 4 && mac_lds_ok(ly, B)) return 5;
     return tiled_ok && B >= 4 ? 1 : 0;
 }
@@ -446,10 +453,11 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         return HE_OK;
     };
     // try every candidate of one knob with the others at their current values; keep the fastest
+    // (pref: a candidate kept unless another is faster by more than `margin` of its time)
     auto pick = [&](int which, uint32_t key_size, uint32_t key_rows, const std::vector<int> &cands,
-                    bool with_sh) -> int {
+                    bool with_sh, int pref = -1000, double margin = 0.0) -> int {
         const auto key = std::make_tuple(which, key_size, key_rows);
-        double best = 1e30;
+        double best = 1e30, pref_ms = -1.0;
         int arg = cands[0];
         for (int c : cands) {
             {
@@ -459,11 +467,13 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
             double ms = 0;
             const int r = time_layer(with_sh, &ms);
             if (r != HE_OK) return r;
+            if (c == pref) pref_ms = ms;
             if (ms < best) {
                 best = ms;
                 arg = c;
             }
         }
+        if (pref_ms >= 0.0 && best > pref_ms * (1.0 - margin)) arg = pref;
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->tuned[key] = arg;
         return HE_OK;
@@ -475,17 +485,44 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
     if (rc == HE_OK) rc = pick(HE_TUNE_NTT_FWD, logN, 2 * fwd_rows, radix, true);
     if (conv) {
         const bool cls = in.flags == HE_PACK_CLASS_INTT;
-        // batch one keeps the fused form (one launch per layer); batches try every form
+        // every form the shape allows.  At batch one the candidates are the fused launch and the
+        // streaming MAC then the tail; mac_variant's fixed rule (streaming for layers with several
+        // input polys and few output rows) is kept unless the other form is 5 % faster, so that
+        // layers timing cannot separate keep the rule's form
         std::vector<int> macs{0};
         if (mac_tiled_ok(ly, B)) macs.push_back(1);
         if (mac_fused_ok(ctx, ly)) macs.push_back(2);
         if (mac_lds_ok(ly, B))
             for (int m : {3, 4, 5, 6}) macs.push_back(m);
-        if (B == 1) macs.clear();
-        if (rc == HE_OK && macs.size() > 1) rc = pick(HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B, macs, true);
+        const uint32_t mac_key = (uint32_t)(((uintptr_t)ly->op) >> 8);
+        const auto mac_tkey = std::make_tuple((int)HE_TUNE_MAC, mac_key, B);
         const uint32_t logm = logN - log2u(in.s);
         const uint32_t rows = B * in.K_out * in.g_o * L;
-        if (rc == HE_OK && cls && logm >= 4) rc = pick(HE_TUNE_TAIL, logm, rows, radix, true);
+        // the tail's radix first, timed under a two-launch MAC form (the fused launch has its own
+        // inverse), so that the MAC forms below are compared against a tuned tail; its key is
+        // shared by the layers of one shape, and the first of them would otherwise see the default
+        if (rc == HE_OK && cls && logm >= 4) {
+            bool temp = false;
+            if (mac_variant(ctx, ly, B) == 2) {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                ctx->tuned[mac_tkey] = 0;
+                temp = true;
+            }
+            rc = pick(HE_TUNE_TAIL, logm, rows, radix, true);
+            if (temp) {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                ctx->tuned.erase(mac_tkey);
+            }
+        }
+        int mac_pref = -1000;
+        if (B == 1 && macs.size() > 1) {
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                ctx->tuned.erase(mac_tkey);
+            }
+            mac_pref = mac_variant(ctx, ly, B);   // the rule, with no tuned value recorded
+        }
+        if (rc == HE_OK && macs.size() > 1) rc = pick(HE_TUNE_MAC, mac_key, B, macs, true, mac_pref, 0.05);
         if (rc == HE_OK && !cls) rc = pick(HE_TUNE_NTT_INV, logN, rows, radix, true);
     } else if (rc == HE_OK) {
         rc = pick(HE_TUNE_NTT_INV, logN, B * in.blocks * L, radix, true);
