@@ -83,3 +83,22 @@ def test_fused_is_the_default_at_batch_one(he):
     ctx.profile_enable(0)
     want = bfv.server_conv(octx, g, c0[0].astype(np.uint64), rho, packing.pack_conv_filters(F, g), sh[0], shn[0])
     assert (got[0] == want).all()
+
+
+def test_streaming_is_the_default_for_few_rows_and_several_inputs(he):
+    """B = 1 with K_in >= 2 and at most 64 output rows (K_out g_o L) takes the streaming MAC and a
+    tail launch instead of the fused launch, with the same words."""
+    N, L = 1024, 2
+    c_i, c_o, H = 16, 12, 14            # s = 4, K_in = 4, K_out = 3, g_o = 4: 24 rows
+    octx, g, F, rho, c0, sh, shn = _case(N, L, c_i, c_o, H, 1, 23, 1)
+    assert g.K_in >= 2 and g.K_out * g.g_o * L <= 64
+    ctx = he.Context(N, L, T)
+    layer = ctx.pack_conv(he.ConvSpec(c_i, c_o, H, H, 3, 1, 1), F, rho)
+    ctx.profile_reset()
+    ctx.profile_enable(he.HE_K_MAC | he.HE_K_TAIL | he.HE_K_MAC_TAIL)
+    got = host(ctx.conv_layer(layer, dev(c0), dev(sh), dev(shn)))
+    assert ctx.profile_read(he.HE_K_MAC_TAIL)[0] == 0
+    assert ctx.profile_read(he.HE_K_MAC)[0] == 1 and ctx.profile_read(he.HE_K_TAIL)[0] == 1
+    ctx.profile_enable(0)
+    want = bfv.server_conv(octx, g, c0[0].astype(np.uint64), rho, packing.pack_conv_filters(F, g), sh[0], shn[0])
+    assert (got[0] == want).all()
