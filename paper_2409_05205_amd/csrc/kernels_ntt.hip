@@ -54,10 +54,13 @@ constexpr int TW_IN_PASS = 2048;
 
 
 // Forward pass P, stage k, group g: the pair (vv, vv + half) uses twiddle
-// psi^brv(2^(S0+k) + ((F >> LO) << k) + (vv >> (RP - k))), slot (2^k - 1) + (vv >> (RP - k)).
+// psi^brv(tb 2^(S0+k) + ((F >> LO) << k) + (vv >> (RP - k))), slot (2^k - 1) + (vv >> (RP - k)).
+// tb = 1 for a whole transform.  Sub-block j of size 2^LOGN of a 2^(LOGN+K)-point transform,
+// after its first K stages, is a 2^LOGN-point transform with tb = 2^K + j: its stage s pairs
+// use psi^brv(2^(s+K) + j 2^s + local block), the whole transform's twiddles.
 template <int LOGN, int LOGR, int TPB, int P>
 __device__ __forceinline__ void fwd_tw_load(PassTw<LOGN, LOGR, TPB> &tw, uint32_t tid, const uint32_t *__restrict__ W,
-                                            const uint32_t *__restrict__ Wsh) {
+                                            const uint32_t *__restrict__ Wsh, uint32_t tb = 1) {
     using PT = PassTw<LOGN, LOGR, TPB>;
     if constexpr (P < PT::PF) {
         constexpr int T = 1 << (LOGN - LOGR);
@@ -72,13 +75,13 @@ __device__ __forceinline__ void fwd_tw_load(PassTw<LOGN, LOGR, TPB> &tw, uint32_
             for (int k = 0; k < RP; ++k)
 #pragma unroll
                 for (int top = 0; top < (1 << k); ++top) {
-                    const uint32_t ti = (1u << (S0 + k)) + (hi << k) + top;
+                    const uint32_t ti = (tb << (S0 + k)) + (hi << k) + top;
                     const int slot = PT::off(P) + g * ((1 << RP) - 1) + (1 << k) - 1 + top;
                     tw.w[slot] = W[ti];
                     tw.ws[slot] = Wsh[ti];
                 }
         }
-        fwd_tw_load<LOGN, LOGR, TPB, P + 1>(tw, tid, W, Wsh);
+        fwd_tw_load<LOGN, LOGR, TPB, P + 1>(tw, tid, W, Wsh, tb);
     }
 }
 
@@ -115,7 +118,7 @@ __device__ __forceinline__ void inv_tw_load(PassTw<LOGN, LOGR, TPB> &tw, uint32_
 template <int LOGN, int LOGR, int TPB, int P>
 __device__ __forceinline__ void fwd_stages(uint32_t (&v)[1 << LOGR], const PassTw<LOGN, LOGR, TPB> &tw, uint32_t tid,
                                            const uint32_t *__restrict__ W, const uint32_t *__restrict__ Wsh,
-                                           uint32_t q, uint32_t q2) {
+                                           uint32_t q, uint32_t q2, uint32_t tb = 1) {
     using PT = PassTw<LOGN, LOGR, TPB>;
     constexpr int T = 1 << (LOGN - LOGR);
     constexpr int S0 = P * LOGR;
@@ -139,7 +142,7 @@ __device__ __forceinline__ void fwd_stages(uint32_t (&v)[1 << LOGR], const PassT
                     wsh = tw.ws[slot];
                 } else {
                     const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
-                    const uint32_t ti = (1u << s) + (idx >> (LOGN - s));
+                    const uint32_t ti = (tb << s) + (idx >> (LOGN - s));
                     w = W[ti];
                     wsh = Wsh[ti];
                 }
@@ -149,11 +152,35 @@ __device__ __forceinline__ void fwd_stages(uint32_t (&v)[1 << LOGR], const PassT
     }
 }
 
-template <int LOGN, int LOGR, int TPB, int P>
+// The value at position sub 2^LS + i after the first K stages of a 2^(LS+K)-point forward
+// transform, from the 2^K inputs x[i + j 2^LS] it depends on (x: the whole row).
+template <int K>
+__device__ __forceinline__ uint32_t fwd_lead(const uint32_t *__restrict__ x, uint32_t i, uint32_t ns, uint32_t sub,
+                                             const uint32_t *__restrict__ W, const uint32_t *__restrict__ Wsh,
+                                             uint32_t q, uint32_t q2) {
+    static_assert(K == 1 || K == 2, "one or two leading stages");
+    if constexpr (K == 1) {
+        uint32_t a = x[i], b = x[i + ns];
+        ct_bfly(a, b, W[1], Wsh[1], q, q2);          // stage 0: (i, i + N/2)
+        return sub ? b : a;
+    } else {
+        uint32_t a0 = x[i], a1 = x[i + ns], a2 = x[i + 2 * ns], a3 = x[i + 3 * ns];
+        ct_bfly(a0, a2, W[1], Wsh[1], q, q2);        // stage 0: (i, i + N/2), (i + N/4, i + 3N/4)
+        ct_bfly(a1, a3, W[1], Wsh[1], q, q2);
+        uint32_t x0 = sub < 2 ? a0 : a2, x1 = sub < 2 ? a1 : a3;
+        const uint32_t ti = 2u + (sub >> 1);         // stage 1: block sub / 2, pair (i, i + N/4)
+        ct_bfly(x0, x1, W[ti], Wsh[ti], q, q2);
+        return (sub & 1u) ? x1 : x0;
+    }
+}
+
+// K = 0: a whole transform of the row `in`.  K > 0: sub-block `sub` of a 2^(LOGN+K)-point
+// transform of the row `in` (its leading K stages formed on load), twiddle base tb = 2^K + sub.
+template <int LOGN, int LOGR, int TPB, int P, int K = 0>
 __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], const PassTw<LOGN, LOGR, TPB> &tw, uint32_t *lds,
                                          uint32_t tid, const uint32_t *__restrict__ in,
                                          const uint32_t *__restrict__ W, const uint32_t *__restrict__ Wsh, uint32_t q,
-                                         uint32_t q2) {
+                                         uint32_t q2, uint32_t tb = 1, uint32_t sub = 0) {
     constexpr int T = 1 << (LOGN - LOGR);
     constexpr int S0 = P * LOGR;
     constexpr int RP = (LOGN - S0 < LOGR) ? (LOGN - S0) : LOGR;
@@ -165,10 +192,15 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], const PassTw<
 #pragma unroll
         for (int vv = 0; vv < (1 << RP); ++vv) {
             const uint32_t idx = gidx<LOGN, LO, RP>(F, vv);
-            v[g * (1 << RP) + vv] = (P == 0) ? in[idx] : lds[lpad(idx)];
+            if constexpr (P > 0)
+                v[g * (1 << RP) + vv] = lds[lpad(idx)];
+            else if constexpr (K == 0)
+                v[g * (1 << RP) + vv] = in[idx];
+            else
+                v[g * (1 << RP) + vv] = fwd_lead<K>(in, idx, 1u << LOGN, sub, W, Wsh, q, q2);
         }
     }
-    fwd_stages<LOGN, LOGR, TPB, P>(v, tw, tid, W, Wsh, q, q2);
+    fwd_stages<LOGN, LOGR, TPB, P>(v, tw, tid, W, Wsh, q, q2, tb);
     if (P > 0) __syncthreads();   // every read of this pass is done before any write
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -180,7 +212,7 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LOGR], const PassTw<
         }
     }
     __syncthreads();
-    if constexpr (S0 + RP < LOGN) fwd_pass<LOGN, LOGR, TPB, P + 1>(v, tw, lds, tid, in, W, Wsh, q, q2);
+    if constexpr (S0 + RP < LOGN) fwd_pass<LOGN, LOGR, TPB, P + 1, K>(v, tw, lds, tid, in, W, Wsh, q, q2, tb, sub);
 }
 
 // PF: twiddles of the first passes prefetched into registers (a launch of a few rows, where
@@ -210,6 +242,47 @@ k_ntt_fwd(FwdJobs jobs, const uint32_t *__restrict__ tw, const uint32_t *__restr
     fwd_tw_load<LOGN, LOGR, TWB, 0>(ptw, tid, W, Wsh);
     uint32_t v[1 << LOGR];
     fwd_pass<LOGN, LOGR, TWB, 0>(v, ptw, lds, tid, in, W, Wsh, q, q2);
+#pragma unroll
+    for (int i = 0; i < (1 << LOGR); ++i) {
+        const uint32_t idx = tid + i * T;
+        uint32_t x = lds[lpad(idx)];
+        x = csub(x, q2);
+        out[idx] = csub(x, q);
+    }
+}
+
+// A launch of few rows leaves most CUs idle while each row's transform is ALU time on one CU.
+// Here 2^K workgroups share a row: after the first K stages the row splits into 2^K independent
+// sub-transforms of N / 2^K points, so workgroup `sub` reads the whole row, forms the K leading
+// stages of its own sub-block on load (fwd_lead) and runs the rest alone; no workgroup waits for
+// another.  The output words and their positions are those of k_ntt_fwd.
+template <int LOGN, int LOGR, int K>
+__global__ void __launch_bounds__(1 << (LOGN - K - LOGR))
+k_ntt_fwd_split(FwdJobs jobs, const uint32_t *__restrict__ tw, const uint32_t *__restrict__ twsh, LimbConsts lc) {
+    constexpr int LS = LOGN - K;
+    constexpr int NS = 1 << LS;
+    constexpr int T = 1 << (LS - LOGR);
+    __shared__ uint32_t lds[NS + (NS >> 5)];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sub = blockIdx.x & ((1u << K) - 1u);
+    uint32_t r = blockIdx.x >> K;
+    const int js = r < jobs.rows0 ? 0 : 1;       // rows of job 0 first, then job 1
+    if (js) r -= jobs.rows0;
+    const RowMap &map = jobs.map[js];
+    const uint32_t l = r % map.L;
+    const uint32_t jb = r / map.L;
+    const uint32_t j = jb % map.J;
+    const uint32_t b = jb / map.J;
+    const uint32_t *in = jobs.src[js] + b * map.src_b + j * map.src_j + l * map.src_l;
+    uint32_t *out = jobs.dst[js] + b * map.dst_b + j * map.dst_j + l * map.dst_l + (size_t)sub * NS;
+    const uint32_t q = lc.l[l].q, q2 = lc.l[l].q2;
+    const uint32_t *W = tw + (size_t)l * (NS << K);
+    const uint32_t *Wsh = twsh + (size_t)l * (NS << K);
+    const uint32_t tb = (1u << K) + sub;
+    PassTw<LS, LOGR, T> ptw;
+    fwd_tw_load<LS, LOGR, T, 0>(ptw, tid, W, Wsh, tb);
+    uint32_t v[1 << LOGR];
+    fwd_pass<LS, LOGR, T, 0, K>(v, ptw, lds, tid, in, W, Wsh, q, q2, tb, sub);
 #pragma unroll
     for (int i = 0; i < (1 << LOGR); ++i) {
         const uint32_t idx = tid + i * T;
@@ -428,9 +501,34 @@ inline int default_logr(int logn, uint32_t rows) {
     return lr < logn ? lr : logn;
 }
 
+// Rows shared by 2^K workgroups when a launch has at most 64 (K = 2) or 128 (K = 1) rows of
+// N >= 4096; 0 otherwise.
+inline int fwd_split_k(int logn, uint32_t rows) {
+    if (logn < 12) return 0;
+    return rows <= 64 ? 2 : (rows <= 128 ? 1 : 0);
+}
+
 template <int LOGN, int LOGR>
 hipError_t fwd_launch(const FwdJobs &jobs, uint32_t rows, const uint32_t *tw, const uint32_t *twsh,
                       const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
+    if constexpr (LOGN >= 12) {
+        // the radix applies to the sub-transforms; one the split cannot take keeps whole rows
+        const int k = fwd_split_k(LOGN, rows);
+        if (k == 2 && valid_variant(LOGN - 2, LOGR)) {
+            if constexpr (valid_variant(LOGN - 2, LOGR)) {
+                HE_LAUNCH(ev, (k_ntt_fwd_split<LOGN, LOGR, 2>), dim3(rows << 2), dim3(1 << (LOGN - 2 - LOGR)), 0, st,
+                          jobs, tw, twsh, lc);
+                return hipGetLastError();
+            }
+        }
+        if (k == 1 && valid_variant(LOGN - 1, LOGR)) {
+            if constexpr (valid_variant(LOGN - 1, LOGR)) {
+                HE_LAUNCH(ev, (k_ntt_fwd_split<LOGN, LOGR, 1>), dim3(rows << 1), dim3(1 << (LOGN - 1 - LOGR)), 0, st,
+                          jobs, tw, twsh, lc);
+                return hipGetLastError();
+            }
+        }
+    }
     if constexpr (valid_variant(LOGN, LOGR)) {
         // a launch of up to one row per CU keeps the twiddle prefetch; larger ones read per pass
         if (rows <= 256)

@@ -32,6 +32,20 @@ def test_ntt_roundtrip_on_device(he, N, L):
         assert Xh[:, l, :].max() < q
 
 
+@pytest.mark.parametrize("N,L", [(4096, 3), (8192, 4), (16384, 6)])
+def test_forward_split_rows_match_whole_rows(he, N, L):
+    """A launch of at most 128 (64) limb rows shares each row between 2 (4) workgroups; the words
+    must be those of the one-workgroup-per-row transform of a larger launch, and round-trip."""
+    ctx = he.Context(N, L, T)
+    R = 256 // L + 1                                # > 128 limb rows: whole rows
+    x = wl.uniform_per_modulus(np.random.default_rng(N + 7), (R,), ctx.primes, N)
+    whole = host(ctx.ntt_forward(dev(x)))
+    for r in (100 // L, 40 // L, 1):                 # 2-way, 4-way, 4-way with one poly
+        part = ctx.ntt_forward(dev(x[:r]))
+        assert (host(part) == whole[:r]).all(), f"{r} polys of {L} limbs"
+        assert (host(ctx.ntt_inverse(part)) == x[:r].astype(np.uint64)).all()
+
+
 @pytest.mark.parametrize("N,L", [(256, 2), (1024, 2)])
 def test_poly_mul_matches_schoolbook(he, N, L):
     ctx = he.Context(N, L, T)
