@@ -47,11 +47,11 @@ PMC_TRAFFIC = {
     # (plan: the MAC form of each of the 20 layers in the measured run, F fused, S split)
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
             "plan": "FSSSSSSFFFFFFFFFFFFS",
-            "sha256": "2bd42d1e0799a5871a2b67403a1f4eb16f61c113b5281ab2d9cce526722071d7",
-            "bytes_per_launch": 18879312},
+            "sha256": "c3223b45608ac5d2826bce86ea425b2e26b45040650d333482d2c3c8d661e85c",
+            "bytes_per_launch": 18882657},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
-                "sha256": "668992c31db973b91bbbf9ed5279e55ca76ceb0aee6a5ca3324c965f38cbb66d",
-                "bytes_per_launch": 1670517},
+                "sha256": "15abb7b7caae536cb277a55783aa9bf077aeef8ef6cd9d59cbed013d113d7106",
+                "bytes_per_launch": 2500907},
 }
 
 
