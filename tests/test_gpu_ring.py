@@ -40,7 +40,8 @@ def test_forward_split_rows_match_whole_rows(he, N, L):
     R = 256 // L + 1                                # > 128 limb rows: whole rows
     x = wl.uniform_per_modulus(np.random.default_rng(N + 7), (R,), ctx.primes, N)
     whole = host(ctx.ntt_forward(dev(x)))
-    for r in (100 // L, 40 // L, 1):                 # 2-way, 4-way, 4-way with one poly
+    # 2-way, 4-way, one poly, and both sides of the 64- and 128-row boundaries
+    for r in sorted({100 // L, 40 // L, 1, 64 // L, 64 // L + 1, 128 // L, 128 // L + 1}):
         part = ctx.ntt_forward(dev(x[:r]))
         assert (host(part) == whole[:r]).all(), f"{r} polys of {L} limbs"
         assert (host(ctx.ntt_inverse(part)) == x[:r].astype(np.uint64)).all()
