@@ -43,12 +43,32 @@ MAD64_PEAK_G = 22400.0
 # HBM traffic per launch from the FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a 256 MiB
 # copy), valid while the kernel source is the one that was measured.
 PMC_TRAFFIC = {
-    # launches carrying the MAC in the plain form: k_mac_tail (conv) and k_mac_full (FC)
-    # (plan: the MAC form of each of the 20 layers in the measured run, F fused, S split)
+    # launches carrying the MAC in the plain form: k_mac_tail (fused) and k_mac_class / k_mac_full
+    # (split), measured per layer of the stack with every layer pinned to each form in turn; the
+    # traffic of a run is the mean over its layers of the entry of the form each layer ran in
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
-            "plan": "FSSSSSSFFFFFFFFFFFFS",
             "sha256": "c3223b45608ac5d2826bce86ea425b2e26b45040650d333482d2c3c8d661e85c",
-            "bytes_per_launch": 18882657},
+            "per_layer": [
+                {"F": 4728523, "S": 2793779},
+                {"F": 21240029, "S": 18389290},
+                {"F": 21239480, "S": 18389143},
+                {"F": 21239243, "S": 18388997},
+                {"F": 21239298, "S": 18388997},
+                {"F": 21239426, "S": 18388851},
+                {"F": 21239298, "S": 18388997},
+                {"F": 40110853, "S": 35688793},
+                {"F": 19035181, "S": 17602629},
+                {"F": 19035145, "S": 17602776},
+                {"F": 19035218, "S": 17602629},
+                {"F": 19035163, "S": 17602629},
+                {"F": 19035236, "S": 17602776},
+                {"F": 36858071, "S": 34640793},
+                {"F": 17949760, "S": 17209445},
+                {"F": 17949669, "S": 17209445},
+                {"F": 17949833, "S": 17209592},
+                {"F": 17949723, "S": 17209445},
+                {"F": 17949796, "S": 17209445},
+                {"F": None, "S": 704442}]},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
                 "sha256": "15abb7b7caae536cb277a55783aa9bf077aeef8ef6cd9d59cbed013d113d7106",
                 "bytes_per_launch": 2500907},
@@ -56,19 +76,25 @@ PMC_TRAFFIC = {
 
 
 def pmc_traffic(kind, plan=None):
-    """Counter-measured HBM bytes per launch, or None once a measured source has changed or the
-    layers' MAC forms (one letter per layer: F fused, S split) differ from the measured run's."""
+    """Counter-measured HBM bytes per launch, or None once a measured source has changed.  For a
+    per-layer table, `plan` gives the MAC form of each layer (F fused, S split) and the result is
+    the mean over the layers; None if a layer ran in a form the table has no entry for."""
     import hashlib
     rec = PMC_TRAFFIC.get(kind)
     if rec is None:
-        return None
-    if plan is not None and rec.get("plan") not in (None, plan):
         return None
     h = hashlib.sha256()
     for src in rec["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
-    return rec["bytes_per_launch"] if h.hexdigest() == rec["sha256"] else None
+    if h.hexdigest() != rec["sha256"]:
+        return None
+    if "per_layer" not in rec:
+        return rec["bytes_per_launch"]
+    table = rec["per_layer"]
+    if plan is None or len(plan) != len(table) or any(row.get(c) is None for c, row in zip(plan, table)):
+        return None
+    return round(sum(row[c] for c, row in zip(plan, table)) / len(table))
 
 
 def log(*a):
@@ -480,6 +506,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="also run one 256 MiB device-to-device copy (known bytes) for counter calibration")
+    ap.add_argument("--pmc-mac-form", choices=["F", "S"], default=None,
+                    help="counter runs: pin every layer of the plain stack to the fused (F) or split (S) MAC "
+                         "form, run only the plain loop and print the plan (the per-layer traffic table)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards across GPUs by "
@@ -499,7 +528,9 @@ def main():
     ctx = he.Context(8192, 4, wl.T_PLAIN)
     st = Stack(he, ctx, wl.CONFIG_PLAIN20_X1, 1, [10], [1], 8192, 4)
     n_layers = len(st.steps)
-    if not args.no_tune:
+    if args.pmc_mac_form is not None:
+        ctx.tune_force(he.HE_TUNE_MAC, 2 if args.pmc_mac_form == "F" else 0)
+    elif not args.no_tune:
         st.autotune()
     sync()
 
@@ -514,6 +545,12 @@ def main():
     with torch.cuda.stream(stream):
         T_plain = time_loop(lambda: st.seq.run(stream), args.steps, args.warmup, sync)
     log(f"plain: {T_plain / args.steps * 1e3:.3f} ms/step")
+    if args.pmc_mac_form is not None:
+        # layer order of the MAC launches above is the stack order, one per layer per call
+        plan = "".join("F" if p == "fused" else "S" for p in st.mac_plan(he))
+        print(json.dumps({"pmc_mac_form": args.pmc_mac_form, "plan": plan,
+                          "calls": args.warmup + args.steps + 1}), flush=True)
+        return
 
     # kernel timing of the same calls (HIP events on the launch stream)
     plan = st.mac_plan(he)

@@ -55,3 +55,18 @@ def test_mac_bytes_and_counts():
     assert st.modmuls() == 64 * 8 * 16 * L * N + 32 * 2 * 1 * L * N
     assert st.butterflies_fwd() == (64 * 4 * L * 2 + 32 * L * 2) * (N // 2) * 13
     assert st.tail_butterflies() == 64 * 16 * L * (M // 2) * 11 + 32 * 1 * L * (N // 2) * 13
+
+
+def test_counter_traffic_follows_the_per_layer_mac_forms():
+    table = bench.PMC_TRAFFIC["mac"]["per_layer"]
+    n = len(table)
+    split = "S" * n
+    assert bench.pmc_traffic("mac", split) == round(sum(r["S"] for r in table) / n)
+    mixed = "F" + "S" * (n - 2) + "S"
+    want = (table[0]["F"] + sum(r["S"] for r in table[1:])) / n
+    assert bench.pmc_traffic("mac", mixed) == round(want)
+    # the FC head has no fused form, a plan of the wrong length matches nothing
+    assert table[-1]["F"] is None
+    assert bench.pmc_traffic("mac", "F" * n) is None
+    assert bench.pmc_traffic("mac", split[:-1]) is None
+    assert bench.pmc_traffic("mac") is None
