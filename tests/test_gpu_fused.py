@@ -102,3 +102,34 @@ def test_streaming_is_the_default_for_few_rows_and_several_inputs(he):
     ctx.profile_enable(0)
     want = bfv.server_conv(octx, g, c0[0].astype(np.uint64), rho, packing.pack_conv_filters(F, g), sh[0], shn[0])
     assert (got[0] == want).all()
+
+
+# (N, L, c_i, c_o, H, B): launches of several hundred output rows (B K_out g_o L), more than
+# the chip has CUs, at M = 4096, 2048 and 512, with ragged last groups.
+MANY = [
+    (4096, 3, 2, 127, 44, 1),    # s = 1, M = 4096: 381 rows
+    (4096, 3, 2, 129, 44, 1),    # 387 rows
+    (8192, 3, 1, 126, 40, 1),    # s = 4, M = 2048: 32 groups of 4, 384 rows, ragged
+    (8192, 3, 1, 124, 40, 1),    # 31 groups: 372 rows
+    (4096, 3, 4, 60, 20, 2),     # s = 8, M = 512: 8 groups of 8 per image, 384 rows, ragged
+    (4096, 3, 4, 60, 20, 1),     # 192 rows
+]
+
+
+@pytest.mark.parametrize("case", MANY, ids=lambda c: "N%d_L%d_c%d-%d_H%d_B%d" % c)
+def test_fused_many_rows_matches_oracle(he, case):
+    N, L, c_i, c_o, H, B = case
+    octx, g, F, rho, c0, sh, shn = _case(N, L, c_i, c_o, H, 1, sum(case), B)
+    fh = packing.pack_conv_filters(F, g)
+    rows = B * g.K_out * g.g_o * L
+    ctx = he.Context(N, L, T)
+    ctx.tune_force(he.HE_TUNE_MAC, 2)
+    layer = ctx.pack_conv(he.ConvSpec(c_i, c_o, H, H, 3, 1, 1), F, rho)
+    ctx.profile_reset()
+    ctx.profile_enable(he.HE_K_MAC_TAIL)
+    got = host(ctx.conv_layer(layer, dev(c0), dev(sh), dev(shn)))
+    assert ctx.profile_read(he.HE_K_MAC_TAIL)[0] == 1
+    ctx.profile_enable(0)
+    for b in range(B):
+        want = bfv.server_conv(octx, g, c0[b].astype(np.uint64), rho, fh, sh[b], shn[b])
+        assert (got[b] == want).all(), f"image {b} of {B}, {rows} rows, s={g.s}"
