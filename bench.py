@@ -47,31 +47,32 @@ PMC_TRAFFIC = {
     # (split), measured per layer of the stack with every layer pinned to each form in turn; the
     # traffic of a run is the mean over its layers of the entry of the form each layer ran in
     "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
-            "sha256": "c3223b45608ac5d2826bce86ea425b2e26b45040650d333482d2c3c8d661e85c",
+            "sha256": "ddf2fb4e3b70cdccf81ed56c02e2b36f8ba2c1dda9e26dc75cc0839a4b6718bf",
             "per_layer": [
-                {"F": 4728523, "S": 2793779},
-                {"F": 21240029, "S": 18389290},
-                {"F": 21239480, "S": 18389143},
-                {"F": 21239243, "S": 18388997},
-                {"F": 21239298, "S": 18388997},
-                {"F": 21239426, "S": 18388851},
-                {"F": 21239298, "S": 18388997},
-                {"F": 40110853, "S": 35688793},
-                {"F": 19035181, "S": 17602629},
-                {"F": 19035145, "S": 17602776},
-                {"F": 19035218, "S": 17602629},
-                {"F": 19035163, "S": 17602629},
-                {"F": 19035236, "S": 17602776},
-                {"F": 36858071, "S": 34640793},
-                {"F": 17949760, "S": 17209445},
-                {"F": 17949669, "S": 17209445},
-                {"F": 17949833, "S": 17209592},
-                {"F": 17949723, "S": 17209445},
-                {"F": 17949796, "S": 17209445},
-                {"F": None, "S": 704442}]},
+                {"F": 4729906, "S": 2793775},
+                {"F": 21240682, "S": 18389255},
+                {"F": 21241011, "S": 18389109},
+                {"F": 21240718, "S": 18388963},
+                {"F": 21240645, "S": 18388963},
+                {"F": 21240627, "S": 18388817},
+                {"F": 21240682, "S": 18389109},
+                {"F": 40113302, "S": 35688525},
+                {"F": 19041807, "S": 17602742},
+                {"F": 19041697, "S": 17602596},
+                {"F": 19041789, "S": 17602596},
+                {"F": 19041515, "S": 17602742},
+                {"F": 19041716, "S": 17602596},
+                {"F": 36865530, "S": 34640929},
+                {"F": 17951146, "S": 17209413},
+                {"F": 17951219, "S": 17209559},
+                {"F": 17951457, "S": 17209413},
+                {"F": 17951164, "S": 17209413},
+                {"F": 17951384, "S": 17209449},
+                {"F": None, "S": 704441}
+            ]},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
-                "sha256": "15abb7b7caae536cb277a55783aa9bf077aeef8ef6cd9d59cbed013d113d7106",
-                "bytes_per_launch": 2500907},
+                "sha256": "d4d5ba2710f6548c279d3d4e646dc285a3f5d523711e5410236c1966cb51d561",
+                "bytes_per_launch": 2833897},
 }
 
 

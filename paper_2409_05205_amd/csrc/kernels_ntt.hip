@@ -680,7 +680,7 @@ hipError_t tail_launch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next
 }
 
 // ------------------------------------------------------------------ fused MAC + residue-class tail
-// One workgroup per output row (b, g, n', l), l fastest.  It accumulates the
+// One workgroup per output row (b, g, n', l).  It accumulates the
 // coefficient-wise products of its channel over all N slots and sums the s
 // slots of each block (as the class-form MAC does), keeps the M = N/s block
 // sums in LDS, inverts them there (the M-point Gentleman-Sande of k_tail_rows)
@@ -694,11 +694,15 @@ constexpr int MT_PF = 8;   // sh' words per thread fetched at entry
 template <int LOGM>
 constexpr int mt_logr() { return LOGM - 10 > 2 ? LOGM - 10 : 2; }
 
+// Workgroups go round-robin over the 8 XCDs.  When the limb count does not divide 8, a
+// limb-fastest order would spread several limbs' input rows over every XCD's L2.
+__host__ __device__ constexpr bool mt_xcd_order(uint32_t L) { return L != 0u && (8u % L) != 0u; }
+
 template <int LOGM>
 __global__ void __launch_bounds__(MT_THREADS)
 k_mac_tail(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ out,
            const uint32_t *__restrict__ sh_next, uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t g_o,
-           uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, const uint32_t *__restrict__ twi,
+           uint32_t K_out, uint32_t L, uint32_t rows, uint32_t logN, uint32_t s_log, const uint32_t *__restrict__ twi,
            const uint32_t *__restrict__ twish, LimbConsts lc) {
     constexpr int LOGR = mt_logr<LOGM>();
     constexpr int M = 1 << LOGM;
@@ -706,9 +710,20 @@ k_mac_tail(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint
     __shared__ uint32_t lds[M + (M >> 5)];
     const uint32_t tid = threadIdx.x;
     const uint32_t tpb = blockDim.x;             // N/4 or MT_THREADS: every thread has the same chunk count
-    uint32_t w = blockIdx.x;
-    const uint32_t l = w % L;
-    w /= L;
+    uint32_t w, l;
+    if (mt_xcd_order(L)) {
+        // limb slowest, each XCD a contiguous range: its workgroups cover one or two limbs, whose
+        // input rows then stay in that XCD's L2 for all of its output rows
+        if (!xcd_logical(blockIdx.x, rows, w)) return;
+        const uint32_t per_limb = rows / L;
+        l = w / per_limb;
+        w %= per_limb;
+    } else {
+        // limb fastest: with L dividing 8, the round-robin dispatch already gives each XCD one limb
+        w = blockIdx.x;
+        l = w % L;
+        w /= L;
+    }
     const uint32_t np = w % g_o;
     w /= g_o;
     const uint32_t g = w % K_out;
@@ -890,11 +905,12 @@ hipError_t launch_mac_tail(const uint32_t *X, const uint32_t *Op, uint32_t *out,
     // s/4 lanes per block within one wave; every thread owns the same number of 4-slot chunks
     if (s > 256 || logm < 4 || logm > 14 || N < 256 || g_o == 0 || g_o > s || Juse == 0) return hipErrorInvalidValue;
     const uint32_t tpb = N / 4 < (uint32_t)MT_THREADS ? N / 4 : (uint32_t)MT_THREADS;
-    const uint32_t grid = B * K_out * g_o * L;
+    const uint32_t rows = B * K_out * g_o * L;
+    const uint32_t grid = mt_xcd_order(L) ? xcd_grid(rows) : rows;
 #define HE_MT(LM)                                                                                                    \
     case LM:                                                                                                         \
         HE_LAUNCH(ev, k_mac_tail<LM>, dim3(grid), dim3(tpb), 0, st, X, Op, out, sh_next, Jtot, Juse, c_o, g_o, K_out, \
-                  L, logN, s_log, twi, twish, lc);                                                                   \
+                  L, rows, logN, s_log, twi, twish, lc);                                                             \
         return hipGetLastError();
     switch (logm) {
         HE_MT(4)

@@ -57,7 +57,21 @@ def test_mac_bytes_and_counts():
     assert st.tail_butterflies() == 64 * 16 * L * (M // 2) * 11 + 32 * 1 * L * (N // 2) * 13
 
 
-def test_counter_traffic_follows_the_per_layer_mac_forms():
+def _current(kind):
+    """The counter record with its hash set to the sources as they are now."""
+    import hashlib
+    import os
+    rec = dict(bench.PMC_TRAFFIC[kind])
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(bench.ROOT, src), "rb") as f:
+            h.update(f.read())
+    rec["sha256"] = h.hexdigest()
+    return rec
+
+
+def test_counter_traffic_follows_the_per_layer_mac_forms(monkeypatch):
+    monkeypatch.setitem(bench.PMC_TRAFFIC, "mac", _current("mac"))
     table = bench.PMC_TRAFFIC["mac"]["per_layer"]
     n = len(table)
     split = "S" * n
@@ -70,3 +84,7 @@ def test_counter_traffic_follows_the_per_layer_mac_forms():
     assert bench.pmc_traffic("mac", "F" * n) is None
     assert bench.pmc_traffic("mac", split[:-1]) is None
     assert bench.pmc_traffic("mac") is None
+    # a kernel source changed since the counters were taken
+    stale = dict(bench.PMC_TRAFFIC["mac"], sha256="0" * 64)
+    monkeypatch.setitem(bench.PMC_TRAFFIC, "mac", stale)
+    assert bench.pmc_traffic("mac", split) is None
