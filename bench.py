@@ -119,19 +119,19 @@ class Stack:
             first, last = k == 0, k == len(self.layers_shape) - 1
             if shp.kind == "conv":
                 spec = he.ConvSpec(shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
-                til = ctx.conv_tiling(spec)
+                til = ctx.geometry(spec)
                 W = wl.layer_weights(cfg, width, k, shp)
-                rho = wl.mask_polys(cfg, width, k, til["K_in"] * shp.c_o, N).reshape(til["K_in"], shp.c_o, N)
+                rho = wl.mask_polys(cfg, width, k, til.K_in * shp.c_o, N).reshape(til.K_in, shp.c_o, N)
                 ly = ctx.pack_conv(spec, W, rho)
                 self.layers.append(ly)
                 B = sum(B_list)
-                c0 = torch.from_numpy(wl.ciphertext_polys(cfg, 0, width, k, B * til["K_in"], ctx.primes, N)
-                                      .reshape(B, til["K_in"], L, N).astype(np.int32)).to(dev)
+                c0 = torch.from_numpy(wl.ciphertext_polys(cfg, 0, width, k, B * til.K_in, ctx.primes, N)
+                                      .reshape(B, til.K_in, L, N).astype(np.int32)).to(dev)
                 sh = None if first else torch.from_numpy(
-                    wl.share_polys(cfg, 0, width, k, B * til["K_in"], N).reshape(B, til["K_in"], N)
+                    wl.share_polys(cfg, 0, width, k, B * til.K_in, N).reshape(B, til.K_in, N)
                     .astype(np.int32)).to(dev)
                 shn = None if last else torch.from_numpy(
-                    wl.share_polys(cfg, 0, width, k, B * til["K_out"], N, "shnext").reshape(B, til["K_out"], N)
+                    wl.share_polys(cfg, 0, width, k, B * til.K_out, N, "shnext").reshape(B, til.K_out, N)
                     .astype(np.int32)).to(dev)
                 self.steps.append((ly, B, c0, sh, shn))
                 self.rows.append(shp.c_o)
@@ -140,12 +140,10 @@ class Stack:
                     fshp = wl.FCShape(shp.n_i, classes)
                     W = wl.layer_weights(cfg, width * 10 + h, k, fshp)
                     bias = wl.layer_bias(cfg, width * 10 + h, k, fshp)
-                    nop = 1 << (classes - 1).bit_length()
-                    if shp.n_i * nop > N:
-                        nop = 1 << ((N // shp.n_i).bit_length() - 1)
-                    blocks = -(-classes // nop)
+                    fspec = he.FCSpec(shp.n_i, classes)
+                    blocks = ctx.geometry(fspec).blocks
                     rho = wl.mask_polys(cfg, width * 10 + h, k, blocks, N)
-                    ly = ctx.pack_fc(he.FCSpec(shp.n_i, classes), W, rho, bias)
+                    ly = ctx.pack_fc(fspec, W, rho, bias)
                     self.layers.append(ly)
                     c0 = torch.from_numpy(wl.ciphertext_polys(cfg, 0, width * 10 + h, k, B, ctx.primes, N)
                                           .astype(np.int32)).to(dev)
@@ -384,16 +382,13 @@ def resnet50_form(he, args, stream, sync):
         W = wl.layer_weights(wl.CONFIG_RESNET50, 0, k, shp)
         if shp.kind == "conv":
             spec = he.ConvSpec(shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
-            til = ctx.conv_tiling(spec)
-            rho = wl.mask_polys(wl.CONFIG_RESNET50, 0, k, til["K_in"] * shp.c_o, N).reshape(til["K_in"], shp.c_o, N)
+            K_in = ctx.geometry(spec).K_in
+            rho = wl.mask_polys(wl.CONFIG_RESNET50, 0, k, K_in * shp.c_o, N).reshape(K_in, shp.c_o, N)
             ly = ctx.pack_conv(spec, W, rho)
         else:
-            nop = 1 << (shp.n_o - 1).bit_length()
-            if shp.n_i * nop > N:
-                nop = 1 << ((N // shp.n_i).bit_length() - 1)
-            blocks = -(-shp.n_o // nop)
-            rho = wl.mask_polys(wl.CONFIG_RESNET50, 0, k, blocks, N)
-            ly = ctx.pack_fc(he.FCSpec(shp.n_i, shp.n_o), W, rho, wl.layer_bias(wl.CONFIG_RESNET50, 0, k, shp))
+            fspec = he.FCSpec(shp.n_i, shp.n_o)
+            rho = wl.mask_polys(wl.CONFIG_RESNET50, 0, k, ctx.geometry(fspec).blocks, N)
+            ly = ctx.pack_fc(fspec, W, rho, wl.layer_bias(wl.CONFIG_RESNET50, 0, k, shp))
         del rho
         i = ly.info
         resident += i.resident_bytes * count[shp]

@@ -120,8 +120,37 @@ int he_pack_filters(he_ctx *ctx, const he_layer_desc *desc, const int8_t *weight
 /* Tiling of a packed layer (the quantities in the comment at the top). */
 int he_layer_info_get(const he_layer *layer, he_layer_info *out);
 
+/*
+ * he_layer_geometry -- the tiling of a layer description before any packing:
+ * s, g_i, g_o, K_in, K_out, padded and output sizes for conv (Eq. k_batch_new
+ * and Eq. i_batch generalised by the rule at the top), n_o', n_i', blocks for
+ * FC (Eq. w(x) formula, Theorem 1), and the bytes the packed layer would keep
+ * resident.  The same rule he_pack_filters applies, so callers size their
+ * buffers from it instead of re-deriving it.  Allocates nothing and touches no
+ * device.  flags as for he_pack_filters (ignored for FC).  HE_EINVAL for a
+ * description the ring cannot hold, HE_EUNSUPPORTED for s > 256.
+ */
+int he_layer_geometry(const he_ctx *ctx, const he_layer_desc *desc, uint32_t flags, he_layer_info *out);
+
 /* Bytes of device workspace a layer call with batch B needs (see *_ws calls). */
 size_t he_layer_workspace_bytes(const he_layer *layer, uint32_t B);
+
+/* Bytes of workspace he_encrypt_c0 and he_poly_mul need for `rows` polynomial rows. */
+size_t he_ctx_workspace_bytes(const he_ctx *ctx, uint32_t rows);
+
+/*
+ * he_workspace_reserve -- make the context-owned workspace of `stream` at
+ * least `bytes` bytes (he_layer_workspace_bytes / he_ctx_workspace_bytes give
+ * the sizes).  The calls that use a context workspace (he_conv_layer,
+ * he_fc_layer, he_conv_layer_ntt, he_fc_layer_ntt, he_encrypt_c0,
+ * he_poly_mul) never allocate: they fail with HE_ENOMEM, before any launch,
+ * when the stream's reserved workspace is smaller than they need.  Growing a
+ * workspace synchronises the device before the old buffer is freed; it must
+ * not run while another host thread issues calls on the same stream.  Calls
+ * on one stream share its workspace (they run in stream order); calls on
+ * different streams need their own reservations.
+ */
+int he_workspace_reserve(he_ctx *ctx, void *stream, size_t bytes);
 
 /*
  * he_conv_layer -- server evaluation of one Conv layer for B images
@@ -132,8 +161,8 @@ size_t he_layer_workspace_bytes(const he_layer *layer, uint32_t B);
  *   d_sh_next  [B][K_out][N]    fresh server share sh', values < t; NULL on
  *                               the last layer
  *   d_out      [B][K_out][L][N] c0^r, residues < q_l
- * Uses a workspace owned by the context (allocated on first use for the
- * largest B seen; concurrent calls on different streams each get their own).
+ * Uses the workspace reserved for `stream` (he_workspace_reserve; HE_ENOMEM
+ * if it is smaller than he_layer_workspace_bytes(layer, B)); allocates nothing.
  */
 int he_conv_layer(he_ctx *ctx, const he_layer *layer, uint32_t B,
                   const uint32_t *d_c0, const uint32_t *d_sh, const uint32_t *d_sh_next,
@@ -177,7 +206,7 @@ int he_fc_layer_ws(he_ctx *ctx, const he_layer *layer, uint32_t B,
  * he_conv_layer_ntt / he_fc_layer_ntt -- the rest of the layer (MAC, inverse,
  * extraction, + Delta sh') from d_x; has_sh = 0 when the layer has no input
  * share (the sh rows of d_x are then not read).  d_sh_next, d_out as for
- * he_conv_layer / he_fc_layer.  Uses the context workspace of the stream.
+ * he_conv_layer / he_fc_layer.  Uses the workspace reserved for the stream.
  * he_conv_layer is he_layer_inputs_ntt followed by he_conv_layer_ntt (same words).
  */
 int he_layer_inputs_ntt(he_ctx *ctx, const he_layer *layer, uint32_t B, const uint32_t *d_c0,
@@ -197,7 +226,7 @@ int he_fc_layer_ntt(he_ctx *ctx, const he_layer *layer, uint32_t B, const uint32
 int he_ntt_forward(he_ctx *ctx, uint32_t rows, const uint32_t *d_in, uint32_t *d_out, void *stream);
 int he_ntt_inverse(he_ctx *ctx, uint32_t rows, const uint32_t *d_in, uint32_t *d_out, void *stream);
 /* d_c[r] = d_a[r] * d_b[r] in Z_q[X]/(X^N + 1), per limb; [rows][L][N] each.
- * d_c must not alias d_a or d_b.  Uses the context workspace. */
+ * d_c must not alias d_a or d_b.  Uses the workspace reserved for the stream. */
 int he_poly_mul(he_ctx *ctx, uint32_t rows, const uint32_t *d_a, const uint32_t *d_b,
                 uint32_t *d_c, void *stream);
 
@@ -239,7 +268,7 @@ int he_profile_reset(he_ctx *ctx);
  * mod q_l.  v, e0: device int32 [rows][N] (small signed), b: device [L][N]
  * residues (public key part), msg: device [rows][N] values < t, out:
  * [rows][L][N].  With v = s, b = a, msg = 0, e0 = -e it is key generation
- * b = -a s + e (Sec. II-A).  Uses the context workspace.
+ * b = -a s + e (Sec. II-A).  Uses the workspace reserved for the stream.
  *
  * he_decrypt -- msg[r][k] = round(t x / Q) mod t, x the CRT lift of
  * x0[r][.][k] + x1[r][.][k] (x1 may be NULL): the scale-and-round of the share
@@ -262,8 +291,9 @@ int he_decrypt(he_ctx *ctx, uint32_t rows, uint32_t M, const uint32_t *d_x0, con
  * buffers, run as one host call or captured once into a HIP graph and replayed.
  * Steps run in order on one stream and share one sequence-owned workspace, so a
  * sequence is for one stream at a time.  Buffers must stay valid while the
- * sequence exists.  Capture needs a non-null stream and turns kernel timing off
- * for the context; after capture no step can be added.
+ * sequence exists.  Capture needs a non-null stream; no timing events are
+ * recorded into the graph (the context's timing setting is left unchanged);
+ * after capture no step can be added.
  */
 typedef struct he_seq he_seq;
 int he_seq_create(he_ctx *ctx, he_seq **out);
@@ -336,10 +366,12 @@ void he_server_free(he_server *srv);
  * batch B one after another: each candidate is timed as a whole layer call on
  * scratch buffers (median of 5, caches evicted before each), and the fastest is
  * kept for later calls with that shape (at B = 1 the MAC form leaves the automatic
- * rule above only for a form at least 5 % faster).  It allocates and frees its scratch
+ * rule above only for a form at least 5 % faster).  Candidates are visible only to
+ * the tuning thread while they are timed; the choices are published when tuning ends
+ * (the MAC form is kept with the layer, per B).  It allocates and frees its scratch
  * (about 512 MiB plus one call's buffers) and synchronises the stream.
- * he_tune_get reads a kept choice back (key: knob, log2 of the transform size,
- * rows per launch; for HE_TUNE_MAC the layer and B).
+ * he_tune_get reads a kept transform choice back (key: knob, log2 of the transform
+ * size, rows per launch); HE_EINVAL for HE_TUNE_MAC, whose choices live with layers.
  */
 enum { HE_TUNE_NTT_FWD = 1, HE_TUNE_NTT_INV = 2, HE_TUNE_TAIL = 3, HE_TUNE_MAC = 4 };
 int he_tune_force(he_ctx *ctx, uint32_t knob, int32_t value);

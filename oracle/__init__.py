@@ -15,7 +15,8 @@ Modules
   bfv      key generation, c0 encryption, server evaluation (Alg. 1 / Alg. 2),
            client evaluation and decryption
   network  integer conv / FC reference, plain-20 harness between layers
-  counts   Table I / Table III operation counts and Table II byte formulas
+  counts   Table I / Table III operation counts (and the generalised packing's
+           per-layer counts that reduce to them) and Table II byte formulas
 
 Parity notes: every function is pinned by a CPU test against a closed form,
 a brute-force definition, an invariant or a value printed in the paper, except

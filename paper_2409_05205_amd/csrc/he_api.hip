@@ -140,6 +140,8 @@ struct he_layer {
     uint32_t *op = nullptr;        // [c_o or blocks][L][2 K_in][N]
     int32_t *bias = nullptr;       // fc: [blocks][n_o_p]
     uint32_t n_rows = 0;           // c_o (conv) or blocks (fc)
+    // MAC form chosen by the autotuner per batch size (guarded by the context's mutex)
+    mutable std::map<uint32_t, int> mac_choice;
 };
 
 namespace {
@@ -157,36 +159,57 @@ size_t layer_ws_bytes(const he_layer *ly, uint32_t B) {
     return align256((size_t)B * 2 * L * N * 4) + align256((size_t)B * in.blocks * L * N * 4);
 }
 
+// The workspace reserved for `st` (he_workspace_reserve); a call never allocates.  Fails with
+// HE_ENOMEM, naming the bytes needed, when nothing or too little was reserved for the stream.
 int ctx_workspace(he_ctx *ctx, hipStream_t st, size_t bytes, void **out) {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    Workspace &w = ctx->ws[st];
-    if (w.bytes < bytes) {
-        if (w.ptr) HE_HIP(hipFree(w.ptr));
-        w.ptr = nullptr;
-        w.bytes = 0;
-        hipError_t e = hipMalloc(&w.ptr, bytes);
-        if (e != hipSuccess) {
-            w.ptr = nullptr;
-            g_last_error = std::string("workspace hipMalloc: ") + hipGetErrorString(e);
-            return HE_ENOMEM;
-        }
-        w.bytes = bytes;
+    auto it = ctx->ws.find(st);
+    if (it == ctx->ws.end() || it->second.bytes < bytes) {
+        g_last_error = "workspace: " + std::to_string(bytes) + " bytes needed on this stream, " +
+                       std::to_string(it == ctx->ws.end() ? 0 : it->second.bytes) +
+                       " reserved (he_workspace_reserve, or pass a workspace to a *_ws call)";
+        return HE_ENOMEM;
     }
-    *out = w.ptr;
+    *out = it->second.ptr;
     return HE_OK;
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Candidate knob values of a running autotune, visible only to the tuning thread, so that calls on
+// other threads keep the published choices while candidates are timed.
+struct TuneTrial {
+    std::map<std::tuple<int, uint32_t, uint32_t>, int> knobs;
+    const he_layer *mac_layer = nullptr;
+    uint32_t mac_B = 0;
+    int mac = -2;   // -2: none under trial
+};
+thread_local const TuneTrial *tl_trial = nullptr;
+// Kernel timing is suppressed on this thread (autotune trials, graph capture).
+thread_local bool tl_no_prof = false;
+
 int knob(he_ctx *ctx, int which, uint32_t logsize, uint32_t rows) {
     const int forced = which == HE_TUNE_NTT_FWD ? ctx->force_fwd
                        : which == HE_TUNE_NTT_INV ? ctx->force_inv
-                       : which == HE_TUNE_TAIL ? ctx->force_tail
-                                               : ctx->force_mac;
-    if (which == HE_TUNE_MAC ? forced >= 0 : forced > 0) return forced;
+                                                  : ctx->force_tail;
+    if (forced > 0) return forced;
+    const auto key = std::make_tuple(which, logsize, rows);
+    if (tl_trial) {
+        auto it = tl_trial->knobs.find(key);
+        if (it != tl_trial->knobs.end()) return it->second;
+    }
     std::lock_guard<std::mutex> lk(ctx->mu);
-    auto it = ctx->tuned.find(std::make_tuple(which, logsize, rows));
-    return it == ctx->tuned.end() ? (which == HE_TUNE_MAC ? -1 : 0) : it->second;
+    auto it = ctx->tuned.find(key);
+    return it == ctx->tuned.end() ? 0 : it->second;
+}
+
+// The MAC form kept for this layer at batch B: a trial value of a running autotune on this thread,
+// else the tuner's published choice, else -1 (automatic).
+int mac_tuned(he_ctx *ctx, const he_layer *ly, uint32_t B) {
+    if (tl_trial && tl_trial->mac != -2 && tl_trial->mac_layer == ly && tl_trial->mac_B == B) return tl_trial->mac;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ly->mac_choice.find(B);
+    return it == ly->mac_choice.end() ? -1 : it->second;
 }
 
 // Conv MAC variant of a layer at batch B: 0 streaming (then tail), 1 register-blocked
@@ -214,7 +237,8 @@ bool mac_lds_ok(const he_layer *ly, uint32_t B) {
 }
 
 int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
-    const int mk = knob(ctx, HE_TUNE_MAC, (uint32_t)(((uintptr_t)ly->op) >> 8), B);
+    int mk = ctx->force_mac;
+    if (mk < 0) mk = mac_tuned(ctx, ly, B);
     const bool tiled_ok = mac_tiled_ok(ly, B), fused_ok = mac_fused_ok(ctx, ly);
     if (mk == 3 || mk == 4 || mk == 5 || mk == 6) return mac_lds_ok(ly, B) ? mk : 0;
     if (mk == 2) return fused_ok ? 2 : 0;
@@ -237,7 +261,7 @@ struct ProfScope {
     uint32_t kind;
     LaunchEv le;
     ProfScope(he_ctx *c, uint32_t k) : ctx(c), kind(k) {
-        if (ctx->prof_mask & kind) {
+        if ((ctx->prof_mask & kind) && !tl_no_prof) {
             if (hipEventCreate(&le.start) != hipSuccess || hipEventCreate(&le.stop) != hipSuccess)
                 le.start = le.stop = nullptr;
         }
@@ -255,6 +279,65 @@ struct ProfScope {
 
 }  // namespace
 
+
+namespace {
+
+// Tiling of a layer description (the rule in include/he.h); cls gets o_n per channel (conv).
+int layer_geometry(const he_ctx *ctx, const he_layer_desc *desc, uint32_t flags, he_layer_info *info,
+                   std::vector<uint32_t> *cls) {
+    const uint32_t N = ctx->N;
+    std::memset(info, 0, sizeof(*info));
+    info->kind = desc->kind;
+    info->N = N;
+    info->L = ctx->L;
+    if (desc->kind == HE_LAYER_CONV) {
+        const uint32_t c_i = desc->c_i, c_o = desc->c_o, H = desc->H, W = desc->W, f = desc->f;
+        if (!c_i || !c_o || !H || !W || !f || !desc->stride) return HE_EINVAL;
+        const uint64_t Hp = (uint64_t)H + 2 * desc->pad, Wp = (uint64_t)W + 2 * desc->pad;
+        if (f > Hp || f > Wp || Hp * Wp > N) return HE_EINVAL;
+        const uint32_t s = pow2_floor((uint32_t)(N / (Hp * Wp)));
+        if (s > 256) return HE_EUNSUPPORTED;
+        info->s = s;
+        info->g_i = c_i < s ? c_i : s;
+        info->g_o = pow2_floor(c_o < s ? c_o : s);
+        info->K_in = (c_i + info->g_i - 1) / info->g_i;
+        info->K_out = (c_o + info->g_o - 1) / info->g_o;
+        info->H_p = (uint32_t)Hp;
+        info->W_p = (uint32_t)Wp;
+        info->H_o = (uint32_t)((Hp - f) / desc->stride + 1);
+        info->W_o = (uint32_t)((Wp - f) / desc->stride + 1);
+        info->flags = flags;
+        if (cls) {
+            cls->resize(c_o);
+            for (uint32_t n = 0; n < c_o; ++n) (*cls)[n] = (n % info->g_o) * (s / info->g_o);
+        }
+        return HE_OK;
+    }
+    if (desc->kind == HE_LAYER_FC) {
+        const uint32_t n_i = desc->n_i, n_o = desc->n_o;
+        if (!n_i || !n_o || n_i > N) return HE_EINVAL;
+        uint32_t nop = 1;
+        while (nop < n_o) nop <<= 1;
+        if ((uint64_t)n_i * nop > N) nop = pow2_floor(N / n_i);
+        info->n_o_p = nop;
+        info->n_i_p = N / nop;
+        info->blocks = (n_o + nop - 1) / nop;
+        info->K_in = 1;
+        info->flags = HE_PACK_FULL_INTT;
+        return HE_OK;
+    }
+    return HE_EINVAL;
+}
+
+}  // namespace
+
+// Library-internal: suppress kernel timing on the calling thread (graph capture); returns the
+// previous setting.
+__attribute__((visibility("hidden"))) bool he_prof_suppress(bool on) {
+    const bool was = tl_no_prof;
+    tl_no_prof = on;
+    return was;
+}
 
 extern "C" {
 
@@ -432,8 +515,12 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
     if (hipMemsetAsync(buf, 0, data_b, st) != hipSuccess || hipEventCreate(&ea) != hipSuccess ||
         hipEventCreate(&eb) != hipSuccess)
         rc = HE_EDEVICE;
-    const uint32_t saved_prof = ctx->prof_mask;
-    ctx->prof_mask = 0;
+    // candidates are set on this thread only; the choices are published once at the end
+    TuneTrial trial;
+    const TuneTrial *saved_trial = tl_trial;
+    const bool saved_noprof = tl_no_prof;
+    tl_trial = &trial;
+    tl_no_prof = true;
 
     // median duration (ms) of one layer call after one untimed call
     auto time_layer = [&](bool with_sh, double *ms_out) -> int {
@@ -453,17 +540,14 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         return HE_OK;
     };
     // try every candidate of one knob with the others at their current values; keep the fastest
-    // (pref: a candidate kept unless another is faster by more than `margin` of its time)
-    auto pick = [&](int which, uint32_t key_size, uint32_t key_rows, const std::vector<int> &cands,
-                    bool with_sh, int pref = -1000, double margin = 0.0) -> int {
-        const auto key = std::make_tuple(which, key_size, key_rows);
+    // (pref: a candidate kept unless another is faster by more than `margin` of its time).
+    // set(c) puts candidate c under trial.
+    auto pick = [&](const std::function<void(int)> &set, const std::vector<int> &cands, bool with_sh, int *chosen,
+                    int pref = -1000, double margin = 0.0) -> int {
         double best = 1e30, pref_ms = -1.0;
         int arg = cands[0];
         for (int c : cands) {
-            {
-                std::lock_guard<std::mutex> lk(ctx->mu);
-                ctx->tuned[key] = c;
-            }
+            set(c);
             double ms = 0;
             const int r = time_layer(with_sh, &ms);
             if (r != HE_OK) return r;
@@ -474,15 +558,23 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
             }
         }
         if (pref_ms >= 0.0 && best > pref_ms * (1.0 - margin)) arg = pref;
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->tuned[key] = arg;
+        set(arg);
+        *chosen = arg;
         return HE_OK;
     };
+    auto knob_setter = [&](int which, uint32_t key_size, uint32_t key_rows) {
+        return std::function<void(int)>([&trial, which, key_size, key_rows](int c) {
+            trial.knobs[std::make_tuple(which, key_size, key_rows)] = c;
+        });
+    };
+    int chosen = 0;
     const std::vector<int> radix{2, 3, 4, 5};
     const uint32_t fwd_rows = (conv ? B * in.K_in : B) * L;
     // a network's first layer has no input share: its forward launch has half the rows
-    if (rc == HE_OK) rc = pick(HE_TUNE_NTT_FWD, logN, fwd_rows, radix, false);
-    if (rc == HE_OK) rc = pick(HE_TUNE_NTT_FWD, logN, 2 * fwd_rows, radix, true);
+    if (rc == HE_OK) rc = pick(knob_setter(HE_TUNE_NTT_FWD, logN, fwd_rows), radix, false, &chosen);
+    if (rc == HE_OK) rc = pick(knob_setter(HE_TUNE_NTT_FWD, logN, 2 * fwd_rows), radix, true, &chosen);
+    bool mac_done = false;
+    int mac_pick = -1;
     if (conv) {
         const bool cls = in.flags == HE_PACK_CLASS_INTT;
         // every form the shape allows.  At batch one the candidates are the fused launch and the
@@ -494,40 +586,35 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         if (mac_fused_ok(ctx, ly)) macs.push_back(2);
         if (mac_lds_ok(ly, B))
             for (int m : {3, 4, 5, 6}) macs.push_back(m);
-        const uint32_t mac_key = (uint32_t)(((uintptr_t)ly->op) >> 8);
-        const auto mac_tkey = std::make_tuple((int)HE_TUNE_MAC, mac_key, B);
+        trial.mac_layer = ly;
+        trial.mac_B = B;
+        trial.mac = -1;   // the automatic rule while the other knobs are tuned
         const uint32_t logm = logN - log2u(in.s);
         const uint32_t rows = B * in.K_out * in.g_o * L;
         // the tail's radix first, timed under a two-launch MAC form (the fused launch has its own
         // inverse), so that the MAC forms below are compared against a tuned tail; its key is
         // shared by the layers of one shape, and the first of them would otherwise see the default
         if (rc == HE_OK && cls && logm >= 4) {
-            bool temp = false;
-            if (mac_variant(ctx, ly, B) == 2) {
-                std::lock_guard<std::mutex> lk(ctx->mu);
-                ctx->tuned[mac_tkey] = 0;
-                temp = true;
-            }
-            rc = pick(HE_TUNE_TAIL, logm, rows, radix, true);
-            if (temp) {
-                std::lock_guard<std::mutex> lk(ctx->mu);
-                ctx->tuned.erase(mac_tkey);
-            }
+            if (mac_variant(ctx, ly, B) == 2) trial.mac = 0;
+            rc = pick(knob_setter(HE_TUNE_TAIL, logm, rows), radix, true, &chosen);
+            trial.mac = -1;
         }
-        int mac_pref = -1000;
-        if (B == 1 && macs.size() > 1) {
-            {
-                std::lock_guard<std::mutex> lk(ctx->mu);
-                ctx->tuned.erase(mac_tkey);
-            }
-            mac_pref = mac_variant(ctx, ly, B);   // the rule, with no tuned value recorded
+        const int mac_pref = (B == 1 && macs.size() > 1) ? mac_variant(ctx, ly, B) : -1000;   // the rule's form
+        if (rc == HE_OK && macs.size() > 1) {
+            rc = pick([&trial](int c) { trial.mac = c; }, macs, true, &mac_pick, mac_pref, 0.05);
+            mac_done = rc == HE_OK;
         }
-        if (rc == HE_OK && macs.size() > 1) rc = pick(HE_TUNE_MAC, mac_key, B, macs, true, mac_pref, 0.05);
-        if (rc == HE_OK && !cls) rc = pick(HE_TUNE_NTT_INV, logN, rows, radix, true);
+        if (rc == HE_OK && !cls) rc = pick(knob_setter(HE_TUNE_NTT_INV, logN, rows), radix, true, &chosen);
     } else if (rc == HE_OK) {
-        rc = pick(HE_TUNE_NTT_INV, logN, B * in.blocks * L, radix, true);
+        rc = pick(knob_setter(HE_TUNE_NTT_INV, logN, B * in.blocks * L), radix, true, &chosen);
     }
-    ctx->prof_mask = saved_prof;
+    tl_trial = saved_trial;
+    tl_no_prof = saved_noprof;
+    if (rc == HE_OK) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (const auto &kv : trial.knobs) ctx->tuned[kv.first] = kv.second;
+        if (mac_done) ly->mac_choice[B] = mac_pick;
+    }
     hipStreamSynchronize(st);
     if (ea) hipEventDestroy(ea);
     if (eb) hipEventDestroy(eb);
@@ -608,46 +695,73 @@ int he_layer_info_get(const he_layer *ly, he_layer_info *out) {
 
 size_t he_layer_workspace_bytes(const he_layer *ly, uint32_t B) { return ly ? layer_ws_bytes(ly, B) : 0; }
 
+int he_layer_geometry(const he_ctx *ctx, const he_layer_desc *desc, uint32_t flags, he_layer_info *out) {
+    if (!ctx || !desc || !out) return HE_EINVAL;
+    if (flags != HE_PACK_CLASS_INTT && flags != HE_PACK_FULL_INTT) return HE_EINVAL;
+    he_layer_info info;
+    const int rc = layer_geometry(ctx, desc, flags, &info, nullptr);
+    if (rc != HE_OK) return rc;
+    const uint64_t rows = desc->kind == HE_LAYER_CONV ? desc->c_o : info.blocks;
+    info.resident_bytes = rows * ctx->L * 2ull * info.K_in * ctx->N * 4 +
+                          (desc->kind == HE_LAYER_FC ? (uint64_t)info.blocks * info.n_o_p * 4 : 0);
+    *out = info;
+    return HE_OK;
+}
+
+size_t he_ctx_workspace_bytes(const he_ctx *ctx, uint32_t rows) {
+    if (!ctx) return 0;
+    const size_t poly = align256((size_t)rows * ctx->L * ctx->N * 4);
+    const size_t enc = poly + align256((size_t)ctx->L * ctx->N * 4);   // he_encrypt_c0: v rows + NTT(b)
+    const size_t mul = 2 * poly;                                        // he_poly_mul: both transforms
+    return enc > mul ? enc : mul;
+}
+
+int he_workspace_reserve(he_ctx *ctx, void *stream, size_t bytes) {
+    if (!ctx) return HE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Workspace &w = ctx->ws[st];
+    if (w.bytes >= bytes) return HE_OK;
+    // the old buffer may still be read by work queued on any stream: let it drain first
+    if (w.ptr) {
+        HE_HIP(hipDeviceSynchronize());
+        HE_HIP(hipFree(w.ptr));
+    }
+    w.ptr = nullptr;
+    w.bytes = 0;
+    const size_t want = align256(bytes > 0 ? bytes : 256);
+    hipError_t e = hipMalloc(&w.ptr, want);
+    if (e != hipSuccess) {
+        w.ptr = nullptr;
+        g_last_error = std::string("workspace hipMalloc: ") + hipGetErrorString(e);
+        return HE_ENOMEM;
+    }
+    w.bytes = want;
+    return HE_OK;
+}
+
 int he_pack_filters(he_ctx *ctx, const he_layer_desc *desc, const int8_t *weights, const uint32_t *rho,
                     const int32_t *bias, uint32_t flags, he_layer **out) {
     if (!ctx || !desc || !weights || !rho || !out) return HE_EINVAL;
     if (flags != HE_PACK_CLASS_INTT && flags != HE_PACK_FULL_INTT) return HE_EINVAL;
     const uint32_t N = ctx->N, L = ctx->L;
     he_layer_info info;
-    std::memset(&info, 0, sizeof(info));
-    info.kind = desc->kind;
-    info.N = N;
-    info.L = L;
+    std::vector<uint32_t> cls;
+    if (desc->kind == HE_LAYER_CONV && bias) return HE_EINVAL;
+    int grc = layer_geometry(ctx, desc, flags, &info, &cls);
+    if (grc != HE_OK) return grc;
     uint32_t K_in = 0, n_rows = 0;
     std::vector<int16_t> fh;   // [K_in][n_rows][N]
     std::vector<int32_t> hbias;
-    std::vector<uint32_t> cls;
     if (desc->kind == HE_LAYER_CONV) {
-        if (bias) return HE_EINVAL;
-        const uint32_t c_i = desc->c_i, c_o = desc->c_o, H = desc->H, W = desc->W, f = desc->f;
-        const uint32_t st = desc->stride, pad = desc->pad;
-        if (!c_i || !c_o || !H || !W || !f || !st) return HE_EINVAL;
-        const uint64_t Hp = (uint64_t)H + 2 * pad, Wp = (uint64_t)W + 2 * pad;
-        if (f > Hp || f > Wp || Hp * Wp > N) return HE_EINVAL;
-        const uint32_t s = pow2_floor((uint32_t)(N / (Hp * Wp)));
-        if (s > 256) return HE_EUNSUPPORTED;
-        info.s = s;
-        info.g_i = c_i < s ? c_i : s;
-        info.g_o = pow2_floor(c_o < s ? c_o : s);
-        info.K_in = (c_i + info.g_i - 1) / info.g_i;
-        info.K_out = (c_o + info.g_o - 1) / info.g_o;
-        info.H_p = (uint32_t)Hp;
-        info.W_p = (uint32_t)Wp;
-        info.H_o = (uint32_t)((Hp - f) / st + 1);
-        info.W_o = (uint32_t)((Wp - f) / st + 1);
-        info.flags = flags;
+        const uint32_t c_i = desc->c_i, c_o = desc->c_o, f = desc->f;
+        const uint32_t s = info.s;
+        const uint64_t Wp = info.W_p;
         K_in = info.K_in;
         n_rows = c_o;
         fh.assign((size_t)K_in * c_o * N, 0);
-        cls.resize(c_o);
         for (uint32_t n = 0; n < c_o; ++n) {
-            const int64_t o_n = (int64_t)(n % info.g_o) * (s / info.g_o);
-            cls[n] = (uint32_t)o_n;
+            const int64_t o_n = cls[n];
             for (uint32_t m = 0; m < c_i; ++m) {
                 const uint32_t j = m / info.g_i, mp = m % info.g_i;
                 for (uint32_t ky = 0; ky < f; ++ky)
@@ -659,17 +773,9 @@ int he_pack_filters(he_ctx *ctx, const he_layer_desc *desc, const int8_t *weight
                     }
             }
         }
-    } else if (desc->kind == HE_LAYER_FC) {
+    } else {
         const uint32_t n_i = desc->n_i, n_o = desc->n_o;
-        if (!n_i || !n_o || n_i > N) return HE_EINVAL;
-        uint32_t nop = 1;
-        while (nop < n_o) nop <<= 1;
-        if ((uint64_t)n_i * nop > N) nop = pow2_floor(N / n_i);
-        info.n_o_p = nop;
-        info.n_i_p = N / nop;
-        info.blocks = (n_o + nop - 1) / nop;
-        info.K_in = 1;
-        info.flags = HE_PACK_FULL_INTT;
+        const uint32_t nop = info.n_o_p;
         K_in = 1;
         n_rows = info.blocks;
         fh.assign((size_t)info.blocks * N, 0);
@@ -688,8 +794,6 @@ int he_pack_filters(he_ctx *ctx, const he_layer_desc *desc, const int8_t *weight
                 }
                 if (bias) hbias[(size_t)b * nop + k] = bias[row];
             }
-    } else {
-        return HE_EINVAL;
     }
 
     he_layer *ly = new (std::nothrow) he_layer();
@@ -754,56 +858,6 @@ int he_pack_filters(he_ctx *ctx, const he_layer_desc *desc, const int8_t *weight
     return HE_OK;
 }
 
-namespace {
-
-// Tiling of a layer description (the rule in include/he.h); cls gets o_n per channel (conv).
-int layer_geometry(const he_ctx *ctx, const he_layer_desc *desc, uint32_t flags, he_layer_info *info,
-                   std::vector<uint32_t> *cls) {
-    const uint32_t N = ctx->N;
-    std::memset(info, 0, sizeof(*info));
-    info->kind = desc->kind;
-    info->N = N;
-    info->L = ctx->L;
-    if (desc->kind == HE_LAYER_CONV) {
-        const uint32_t c_i = desc->c_i, c_o = desc->c_o, H = desc->H, W = desc->W, f = desc->f;
-        if (!c_i || !c_o || !H || !W || !f || !desc->stride) return HE_EINVAL;
-        const uint64_t Hp = (uint64_t)H + 2 * desc->pad, Wp = (uint64_t)W + 2 * desc->pad;
-        if (f > Hp || f > Wp || Hp * Wp > N) return HE_EINVAL;
-        const uint32_t s = pow2_floor((uint32_t)(N / (Hp * Wp)));
-        if (s > 256) return HE_EUNSUPPORTED;
-        info->s = s;
-        info->g_i = c_i < s ? c_i : s;
-        info->g_o = pow2_floor(c_o < s ? c_o : s);
-        info->K_in = (c_i + info->g_i - 1) / info->g_i;
-        info->K_out = (c_o + info->g_o - 1) / info->g_o;
-        info->H_p = (uint32_t)Hp;
-        info->W_p = (uint32_t)Wp;
-        info->H_o = (uint32_t)((Hp - f) / desc->stride + 1);
-        info->W_o = (uint32_t)((Wp - f) / desc->stride + 1);
-        info->flags = flags;
-        if (cls) {
-            cls->resize(c_o);
-            for (uint32_t n = 0; n < c_o; ++n) (*cls)[n] = (n % info->g_o) * (s / info->g_o);
-        }
-        return HE_OK;
-    }
-    if (desc->kind == HE_LAYER_FC) {
-        const uint32_t n_i = desc->n_i, n_o = desc->n_o;
-        if (!n_i || !n_o || n_i > N) return HE_EINVAL;
-        uint32_t nop = 1;
-        while (nop < n_o) nop <<= 1;
-        if ((uint64_t)n_i * nop > N) nop = pow2_floor(N / n_i);
-        info->n_o_p = nop;
-        info->n_i_p = N / nop;
-        info->blocks = (n_o + nop - 1) / nop;
-        info->K_in = 1;
-        info->flags = HE_PACK_FULL_INTT;
-        return HE_OK;
-    }
-    return HE_EINVAL;
-}
-
-}  // namespace
 
 int he_pack_operands(he_ctx *ctx, const he_layer_desc *desc, const uint32_t *a, const uint32_t *b, uint32_t flags,
                      he_layer **out) {

@@ -165,3 +165,7 @@ hipError_t launch_scale_operands(uint32_t *Op, const uint32_t *xinv, const uint3
 // c[r][l][k] = a[r][l][k] * b[r][l][k] mod q_l
 hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t rows, uint32_t L,
                                 uint32_t N, const LimbConsts &lc, hipStream_t st);
+
+// Library-internal (he_api.hip): suppress kernel timing on the calling thread, e.g. while a
+// graph is captured; returns the previous setting.
+bool he_prof_suppress(bool on);

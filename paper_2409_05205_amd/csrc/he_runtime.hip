@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/he.h"
+#include "he_kernels.h"
 
 namespace {
 
@@ -92,9 +93,12 @@ int he_seq_capture(he_seq *s, void *stream) {
     if (!s || !stream) return HE_EINVAL;   // the null stream cannot be captured
     if (s->exec) return HE_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    he_profile_enable(s->ctx, 0);           // no timing events inside a graph
+    // no timing events inside a graph: timing is suppressed on this thread during the capture
+    // only, so the context's profiling setting is left as the caller set it
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return HE_EDEVICE;
+    const bool was = he_prof_suppress(true);
     int rc = run_steps(s, st);
+    he_prof_suppress(was);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(st, &g);
     if (rc != HE_OK) {

@@ -502,9 +502,34 @@ inline int default_logr(int logn, uint32_t rows) {
 }
 
 // Rows shared by 2^K workgroups when a launch has at most 64 (K = 2) or 128 (K = 1) rows of
-// N >= 4096; 0 otherwise.
-inline int fwd_split_k(int logn, uint32_t rows) {
-    if (logn < 12) return 0;
+// N >= 4096; 0 otherwise.  A shared row is read whole by each of its 2^K workgroups while each
+// writes only its own sub-block, so a launch that transforms any row in place (destination
+// overlapping the source) keeps whole rows: one workgroup per row reads all of it before its
+// first store.
+inline bool fwd_job_in_place(const FwdJobs &jobs, uint32_t rows, uint32_t n) {
+    uintptr_t lo[2][2], hi[2][2];   // [job][source, destination] byte ranges
+    int nj = 0;
+    for (int i = 0; i < 2; ++i) {
+        const uint32_t jr = i == 0 ? (rows < jobs.rows0 ? rows : jobs.rows0) : (rows > jobs.rows0 ? rows - jobs.rows0 : 0);
+        if (jr == 0) continue;
+        const RowMap &m = jobs.map[i];
+        const uint64_t nb = (jr + m.J * m.L - 1) / (m.J * m.L);   // images of the job
+        const uint64_t se = (nb - 1) * m.src_b + (m.J - 1) * m.src_j + (m.L - 1) * m.src_l + n;
+        const uint64_t de = (nb - 1) * m.dst_b + (m.J - 1) * m.dst_j + (m.L - 1) * m.dst_l + n;
+        lo[nj][0] = (uintptr_t)jobs.src[i];
+        hi[nj][0] = lo[nj][0] + se * 4;
+        lo[nj][1] = (uintptr_t)jobs.dst[i];
+        hi[nj][1] = lo[nj][1] + de * 4;
+        ++nj;
+    }
+    for (int a = 0; a < nj; ++a)
+        for (int b = 0; b < nj; ++b)
+            if (lo[a][0] < hi[b][1] && lo[b][1] < hi[a][0]) return true;
+    return false;
+}
+
+inline int fwd_split_k(int logn, uint32_t rows, bool in_place) {
+    if (logn < 12 || in_place) return 0;
     return rows <= 64 ? 2 : (rows <= 128 ? 1 : 0);
 }
 
@@ -513,7 +538,7 @@ hipError_t fwd_launch(const FwdJobs &jobs, uint32_t rows, const uint32_t *tw, co
                       const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
     if constexpr (LOGN >= 12) {
         // the radix applies to the sub-transforms; one the split cannot take keeps whole rows
-        const int k = fwd_split_k(LOGN, rows);
+        const int k = fwd_split_k(LOGN, rows, fwd_job_in_place(jobs, rows, 1u << LOGN));
         if (k == 2 && valid_variant(LOGN - 2, LOGR)) {
             if constexpr (valid_variant(LOGN - 2, LOGR)) {
                 HE_LAUNCH(ev, (k_ntt_fwd_split<LOGN, LOGR, 2>), dim3(rows << 2), dim3(1 << (LOGN - 2 - LOGR)), 0, st,

@@ -34,6 +34,7 @@ EXPORTED = [
     "he_tune_force", "he_autotune_layer", "he_tune_get",
     "he_layer_inputs_ntt", "he_conv_layer_ntt", "he_fc_layer_ntt",
     "he_pack_operands", "he_client_masks", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
+    "he_layer_geometry", "he_ctx_workspace_bytes", "he_workspace_reserve",
 ]
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
 HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL = 1, 2, 4, 8, 16
@@ -87,6 +88,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_layer_info_get.argtypes = [VP, P(LayerInfo)]
     lib.he_layer_workspace_bytes.argtypes = [VP, U32]
     lib.he_layer_workspace_bytes.restype = SZ
+    lib.he_layer_geometry.argtypes = [VP, P(LayerDesc), U32, P(LayerInfo)]
+    lib.he_ctx_workspace_bytes.argtypes = [VP, U32]
+    lib.he_ctx_workspace_bytes.restype = SZ
+    lib.he_workspace_reserve.argtypes = [VP, VP, SZ]
     for name in ("he_conv_layer", "he_fc_layer"):
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
     for name in ("he_conv_layer_ws", "he_fc_layer_ws"):
@@ -132,7 +137,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name not in ("he_layer_workspace_bytes", "he_strerror", "he_last_error", "he_free", "he_free_layer",
-                        "he_seq_length", "he_seq_free", "he_server_requests", "he_server_free"):
+                        "he_seq_length", "he_seq_free", "he_server_requests", "he_server_free",
+                        "he_ctx_workspace_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -187,6 +193,12 @@ class FCSpec:
     n_o: int
 
 
+def _desc(spec) -> LayerDesc:
+    if isinstance(spec, FCSpec):
+        return LayerDesc(HE_LAYER_FC, 0, 0, 0, 0, 0, 0, 0, spec.n_i, spec.n_o)
+    return LayerDesc(HE_LAYER_CONV, spec.c_i, spec.c_o, spec.H, spec.W, spec.f, spec.stride, spec.pad, 0, 0)
+
+
 class Layer:
     """A packed layer: NTT-domain operands resident on the device."""
 
@@ -235,6 +247,24 @@ class Context:
         self.N, self.L, self.t = N, L, t
         self.primes = [int(x) for x in ps]
         self.delta_l = [int(x) for x in ds]
+        self._reserved = {}       # stream handle -> bytes reserved with he_workspace_reserve
+
+    def reserve(self, nbytes: int, stream=None) -> None:
+        """Grow the context workspace of `stream` to at least `nbytes` (he_workspace_reserve).  The
+        layer calls below reserve what they need on first use; a caller that must not allocate later
+        (graph capture, a serving loop) reserves up front."""
+        h = _stream(stream)
+        if self._reserved.get(h, 0) >= nbytes:
+            return
+        _check(load_library().he_workspace_reserve(self.handle, h, nbytes), "he_workspace_reserve")
+        self._reserved[h] = nbytes
+
+    def geometry(self, spec, flags: int = HE_PACK_CLASS_INTT) -> "LayerInfo":
+        """The library's tiling of a layer description, before packing (he_layer_geometry)."""
+        info = LayerInfo()
+        _check(load_library().he_layer_geometry(self.handle, ctypes.byref(_desc(spec)), flags, ctypes.byref(info)),
+               "he_layer_geometry")
+        return info
 
     # ---------------------------------------------------------- packing
     def pack_conv(self, spec, weights: np.ndarray, rho: np.ndarray, flags: int = HE_PACK_CLASS_INTT) -> Layer:
@@ -242,10 +272,10 @@ class Context:
         if w.shape != (spec.c_o, spec.c_i, spec.f, spec.f):
             raise ValueError(f"weights shape {w.shape}")
         r = np.ascontiguousarray(np.asarray(rho, dtype=np.uint32))
-        d = LayerDesc(HE_LAYER_CONV, spec.c_i, spec.c_o, spec.H, spec.W, spec.f, spec.stride, spec.pad, 0, 0)
-        info = self.conv_tiling(spec)
-        if r.shape != (info["K_in"], spec.c_o, self.N):
-            raise ValueError(f"rho shape {r.shape}, expected {(info['K_in'], spec.c_o, self.N)}")
+        d = _desc(spec)
+        info = self.geometry(spec, flags)
+        if r.shape != (info.K_in, spec.c_o, self.N):
+            raise ValueError(f"rho shape {r.shape}, expected {(info.K_in, spec.c_o, self.N)}")
         h = ctypes.c_void_p()
         _check(load_library().he_pack_filters(self.handle, ctypes.byref(d), w.ctypes.data, r.ctypes.data, None,
                                               flags, ctypes.byref(h)), "he_pack_filters")
@@ -257,7 +287,10 @@ class Context:
             raise ValueError(f"weights shape {w.shape}")
         r = np.ascontiguousarray(np.asarray(rho, dtype=np.uint32))
         b = None if bias is None else np.ascontiguousarray(np.asarray(bias, dtype=np.int32))
-        d = LayerDesc(HE_LAYER_FC, 0, 0, 0, 0, 0, 0, 0, spec.n_i, spec.n_o)
+        d = _desc(spec)
+        info = self.geometry(spec)
+        if r.shape != (info.blocks, self.N):
+            raise ValueError(f"rho shape {r.shape}, expected {(info.blocks, self.N)}")
         h = ctypes.c_void_p()
         _check(load_library().he_pack_filters(self.handle, ctypes.byref(d), w.ctypes.data, r.ctypes.data,
                                               None if b is None else b.ctypes.data, 0, ctypes.byref(h)),
@@ -275,12 +308,8 @@ class Context:
         b = np.ascontiguousarray(np.asarray(b, dtype=np.uint32))
         if a.shape != b.shape:
             raise ValueError("a and b must have the same shape")
-        if isinstance(spec, FCSpec):
-            d = LayerDesc(HE_LAYER_FC, 0, 0, 0, 0, 0, 0, 0, spec.n_i, spec.n_o)
-            kind = HE_LAYER_FC
-        else:
-            d = LayerDesc(HE_LAYER_CONV, spec.c_i, spec.c_o, spec.H, spec.W, spec.f, spec.stride, spec.pad, 0, 0)
-            kind = HE_LAYER_CONV
+        d = _desc(spec)
+        kind = HE_LAYER_FC if isinstance(spec, FCSpec) else HE_LAYER_CONV
         h = ctypes.c_void_p()
         _check(load_library().he_pack_operands(self.handle, ctypes.byref(d), a.ctypes.data, b.ctypes.data, flags,
                                                ctypes.byref(h)), "he_pack_operands")
@@ -313,6 +342,7 @@ class Context:
         if out is None:
             out = torch.empty((rows, self.L, self.N), dtype=torch.int32, device=v.device)
         _check_dev(out, (rows, self.L, self.N), "out")
+        self.reserve(int(load_library().he_ctx_workspace_bytes(self.handle, rows)), stream)
         _check(load_library().he_encrypt_c0(self.handle, rows, _ptr(v), _ptr(b), _ptr(msg), _ptr(e0), _ptr(out),
                                             _stream(stream)), "he_encrypt_c0")
         return out
@@ -330,14 +360,6 @@ class Context:
                "he_decrypt")
         return out
 
-    def conv_tiling(self, spec) -> dict:
-        """The tiling rule of include/he.h (host arithmetic only, for sizing buffers)."""
-        Hp, Wp = spec.H + 2 * spec.pad, spec.W + 2 * spec.pad
-        s = 1 << ((self.N // (Hp * Wp)).bit_length() - 1)
-        g_i = min(spec.c_i, s)
-        g_o = 1 << (min(spec.c_o, s).bit_length() - 1)
-        return dict(s=s, g_i=g_i, g_o=g_o, K_in=-(-spec.c_i // g_i), K_out=-(-spec.c_o // g_o))
-
     # ---------------------------------------------------------- layer calls
     def conv_layer(self, layer: Layer, c0, sh=None, sh_next=None, out=None, stream=None, workspace=None):
         import torch
@@ -351,6 +373,7 @@ class Context:
         _check_dev(out, (B, i.K_out, self.L, self.N), "out")
         lib = load_library()
         if workspace is None:
+            self.reserve(layer.workspace_bytes(B), stream)
             rc = lib.he_conv_layer(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out),
                                    _stream(stream))
         else:
@@ -371,6 +394,7 @@ class Context:
         _check_dev(out, (B, i.blocks, self.L, i.n_o_p), "out")
         lib = load_library()
         if workspace is None:
+            self.reserve(layer.workspace_bytes(B), stream)
             rc = lib.he_fc_layer(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out),
                                  _stream(stream))
         else:
@@ -419,6 +443,7 @@ class Context:
         if out is None:
             out = torch.empty(shape, dtype=torch.int32, device=x.device)
         _check_dev(out, shape, "out")
+        self.reserve(layer.workspace_bytes(B), stream)
         _check(fn(self.handle, layer.handle, B, _ptr(x), 1 if has_sh else 0, _ptr(sh_next), _ptr(out),
                   _stream(stream)), name)
         return out
@@ -446,6 +471,7 @@ class Context:
         _check_dev(a, (rows, self.L, self.N), "a")
         _check_dev(b, (rows, self.L, self.N), "b")
         out = torch.empty_like(a) if out is None else out
+        self.reserve(int(load_library().he_ctx_workspace_bytes(self.handle, rows)), stream)
         _check(load_library().he_poly_mul(self.handle, rows, _ptr(a), _ptr(b), _ptr(out), _stream(stream)),
                "he_poly_mul")
         return out

@@ -40,16 +40,13 @@ def pack_variant(width: int, classes: int, ctx: "he.Context", cfg: int = wl.CONF
         W = wl.layer_weights(cfg, width, k, shp)
         if shp.kind == "conv":
             spec = he.ConvSpec(shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
-            til = ctx.conv_tiling(spec)
-            rho = wl.mask_polys(cfg, width, k, til["K_in"] * shp.c_o, N).reshape(til["K_in"], shp.c_o, N)
+            K_in = ctx.geometry(spec).K_in
+            rho = wl.mask_polys(cfg, width, k, K_in * shp.c_o, N).reshape(K_in, shp.c_o, N)
             v.layers.append(ctx.pack_conv(spec, W, rho))
         else:
-            nop = 1 << (shp.n_o - 1).bit_length()
-            if shp.n_i * nop > N:
-                nop = 1 << ((N // shp.n_i).bit_length() - 1)
-            blocks = -(-shp.n_o // nop)
-            rho = wl.mask_polys(cfg, width, k, blocks, N)
-            v.layers.append(ctx.pack_fc(he.FCSpec(shp.n_i, shp.n_o), W, rho, wl.layer_bias(cfg, width, k, shp)))
+            spec = he.FCSpec(shp.n_i, shp.n_o)
+            rho = wl.mask_polys(cfg, width, k, ctx.geometry(spec).blocks, N)
+            v.layers.append(ctx.pack_fc(spec, W, rho, wl.layer_bias(cfg, width, k, shp)))
     return v
 
 
@@ -128,18 +125,20 @@ def run_trace(variants: List[Variant], buffers: List[List[LayerBuffers]], arriva
 
 
 def latency_stats(res, warmup: int):
-    lat = (res["complete"] - res["arrival"])[warmup:]
+    """Latency percentiles and throughput over the requests after `warmup` that succeeded; a failed
+    request (e.g. rejected for memory at dispatch) completes at once and would flatter both."""
     ok = res["status"][warmup:] == 0
+    lat = (res["complete"] - res["arrival"])[warmup:][ok]
     a = res["arrival"][warmup:]
-    c = res["complete"][warmup:]
-    span = c.max() - a.min() if len(a) else float("nan")
+    c = res["complete"][warmup:][ok]
+    span = c.max() - a.min() if len(c) else float("nan")
     return {
-        "requests": int(len(lat)),
+        "requests": int(len(ok)),
         "failed": int((~ok).sum()),
-        "p50_ms": float(np.percentile(lat, 50) * 1e3),
-        "p99_ms": float(np.percentile(lat, 99) * 1e3),
-        "mean_ms": float(lat.mean() * 1e3),
-        "layers_per_s": float(len(lat) / span),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
+        "p99_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
+        "mean_ms": float(lat.mean() * 1e3) if len(lat) else None,
+        "layers_per_s": float(len(lat) / span) if len(lat) else 0.0,
         "mean_batch": float(res["batch"][warmup:].mean()),
     }
 
@@ -180,19 +179,22 @@ def run_clients(variant: Variant, buffers: List[LayerBuffers], clients: int, str
 def client_stats(res):
     """Per-inference latency (first layer issued to last layer returned) and throughput."""
     index = res["index"]
-    start = res["arrival"][index[:, 0]]
-    end = res["complete"][index[:, -1]]
+    ok_req = res["status"] == 0
+    # an inference counts only when every one of its layers succeeded (a failure fails its dependants)
+    ok_inf = ok_req[index].all(axis=1)
+    start = res["arrival"][index[ok_inf, 0]]
+    end = res["complete"][index[ok_inf, -1]]
     inf = end - start
-    lat = res["complete"] - res["arrival"]
-    span = res["complete"].max() - res["arrival"].min()
+    lat = (res["complete"] - res["arrival"])[ok_req]
+    span = res["complete"][ok_req].max() - res["arrival"].min() if ok_req.any() else float("nan")
     return {
         "clients": int(index.shape[0]),
         "requests": int(index.size),
-        "failed": int((res["status"] != 0).sum()),
-        "inference_p50_ms": float(np.percentile(inf, 50) * 1e3),
-        "inference_p99_ms": float(np.percentile(inf, 99) * 1e3),
-        "layer_p50_ms": float(np.percentile(lat, 50) * 1e3),
-        "layer_p99_ms": float(np.percentile(lat, 99) * 1e3),
-        "layers_per_s": float(index.size / span),
+        "failed": int((~ok_req).sum()),
+        "inference_p50_ms": float(np.percentile(inf, 50) * 1e3) if len(inf) else None,
+        "inference_p99_ms": float(np.percentile(inf, 99) * 1e3) if len(inf) else None,
+        "layer_p50_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
+        "layer_p99_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
+        "layers_per_s": float(ok_req.sum() / span) if ok_req.any() else 0.0,
         "mean_batch": float(res["batch"].mean()),
     }

@@ -70,3 +70,12 @@ def test_null_handles_rejected(lib):
     assert lib.he_pack_filters(None, None, None, None, None, 0, None) == he.HE_EINVAL
     assert lib.he_layer_workspace_bytes(None, 4) == 0
     assert lib.he_strerror(he.HE_EINVAL) == b"invalid argument"
+
+
+def test_new_calls_reject_null_handles(lib):
+    from paper_2409_05205_amd import he
+    info = he.LayerInfo()
+    d = he.LayerDesc(he.HE_LAYER_CONV, 3, 16, 32, 32, 3, 1, 1, 0, 0)
+    assert lib.he_layer_geometry(None, ctypes.byref(d), 0, ctypes.byref(info)) == he.HE_EINVAL
+    assert lib.he_workspace_reserve(None, None, 1 << 20) == he.HE_EINVAL
+    assert lib.he_ctx_workspace_bytes(None, 4) == 0

@@ -17,13 +17,13 @@ def _build(he, ctx, N, L, rng):
     shapes = [(4, 16, 6, 1), (16, 16, 6, 1), (16, 32, 6, 2)]
     for k, (ci, co, H, st) in enumerate(shapes):
         spec = he.ConvSpec(ci, co, H, H, 3, st, 1)
-        til = ctx.conv_tiling(spec)
-        ly = ctx.pack_conv(spec, rng.integers(-7, 8, (co, ci, 3, 3)), rng.integers(0, T, (til["K_in"], co, N)),
+        til = ctx.geometry(spec)
+        ly = ctx.pack_conv(spec, rng.integers(-7, 8, (co, ci, 3, 3)), rng.integers(0, T, (til.K_in, co, N)),
                            flags=k % 2)
         B = 3
-        c0 = dev(np.stack([wl.uniform_per_modulus(rng, (til["K_in"],), ctx.primes, N) for _ in range(B)]))
-        sh = None if k == 0 else dev(rng.integers(0, T, (B, til["K_in"], N)))
-        shn = dev(rng.integers(0, T, (B, til["K_out"], N)))
+        c0 = dev(np.stack([wl.uniform_per_modulus(rng, (til.K_in,), ctx.primes, N) for _ in range(B)]))
+        sh = None if k == 0 else dev(rng.integers(0, T, (B, til.K_in, N)))
+        shn = dev(rng.integers(0, T, (B, til.K_out, N)))
         steps.append((ly, c0, sh, shn))
     fly = ctx.pack_fc(he.FCSpec(32, 10), rng.integers(-7, 8, (10, 32)), rng.integers(0, T, (1, N)),
                       rng.integers(-7, 8, 10))

@@ -30,9 +30,9 @@ def setup():
     for shp in shapes:
         if shp.kind == "conv":
             spec = he.ConvSpec(shp.c_i, shp.c_o, shp.H, shp.W, 3, shp.stride, 1)
-            til = ctx.conv_tiling(spec)
+            til = ctx.geometry(spec)
             v.layers.append(ctx.pack_conv(spec, rng.integers(-7, 8, (shp.c_o, shp.c_i, 3, 3)),
-                                          rng.integers(0, T, (til["K_in"], shp.c_o, N))))
+                                          rng.integers(0, T, (til.K_in, shp.c_o, N))))
         else:
             v.layers.append(ctx.pack_fc(he.FCSpec(32, 10), rng.integers(-7, 8, (10, 32)),
                                         rng.integers(0, T, (1, N)), rng.integers(-7, 8, 10)))

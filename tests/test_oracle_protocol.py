@@ -116,3 +116,117 @@ def test_harness_requant():
     assert network.relu_requant(np.array([-1, 15])).tolist() == [0, 15]
     x = np.arange(2 * 8 * 8).reshape(2, 8, 8)
     assert network.gap(x).tolist() == [31, 95]
+
+
+# ------------------------------------------------------------------ the RLWE identity (Sec. II-A)
+def _schoolbook_limbs(ctx, a_limbs, b_signed):
+    """a * b per limb by the schoolbook definition (independent of the oracle's NTT)."""
+    from oracle import ring
+    return np.stack([ring.negacyclic_schoolbook(a_limbs[l], b_signed, q) for l, q in enumerate(ctx.primes)])
+
+
+def _rlwe_case(ctx, seed):
+    rng = np.random.default_rng(seed)
+    N = ctx.N
+    s = wl.ternary(rng, N)
+    a = wl.uniform_per_modulus(rng, (), ctx.primes, N).astype(np.uint64)
+    e = wl.gaussian(rng, N)
+    v = wl.encryption_v(rng, N)
+    e0 = wl.gaussian(rng, N)
+    e1 = wl.gaussian(rng, N)
+    i = rng.integers(0, T, N)
+    return s, a, e, v, e0, e1, i
+
+
+def _decrypt_with_key(ctx, c0, a, s, v, e1):
+    """The second ciphertext element of the same encryption, c1 = -(v a + e1) (the negation of
+    the fresh c1 = v a + e1 of Eq. encryption), then c0 + c1 s and the scale-and-round."""
+    from oracle import ring
+    va = _schoolbook_limbs(ctx, a, v)
+    c1 = np.stack([(np.uint64(q) - (va[l] + ring.reduce_signed(e1, q)) % np.uint64(q)) % np.uint64(q)
+                   for l, q in enumerate(ctx.primes)])
+    c1s = _schoolbook_limbs(ctx, c1, s)
+    x = np.stack([(c0[l] + c1s[l]) % np.uint64(q) for l, q in enumerate(ctx.primes)])
+    return bfv.decrypt(ctx, x[None])[0]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_keygen_encrypt_decrypt_rlwe_identity(seed):
+    """Pins keygen (b = -a s + e), encrypt_c0 and decrypt together through the identity of
+    Eq. encryption / Eq. decryption: with c1 = -(v a + e1), c0 + c1 s = -(Delta i + v e + e0 + e1 s),
+    which decrypts to -i mod t.  Products by the schoolbook definition, not the oracle's NTT."""
+    ctx = bfv.make_ctx(64, 2, T)
+    s, a, e, v, e0, e1, i = _rlwe_case(ctx, seed)
+    b = bfv.keygen(ctx, s, a, e)
+    # b + a s = e per limb (the definition of the public key)
+    as_ = _schoolbook_limbs(ctx, a, s)
+    from oracle import ring
+    for l, q in enumerate(ctx.primes):
+        assert ((b[l] + as_[l]) % np.uint64(q) == ring.reduce_signed(e, q)).all()
+    c0 = bfv.encrypt_c0(ctx, i, v, e0, b)
+    assert (_decrypt_with_key(ctx, c0, a, s, v, e1) == (-i) % T).all()
+
+
+def test_keygen_sign_flip_fails():
+    """Planted mistake: b = a s + e (sign of a s flipped) must break the identity, since then
+    c0 + c1 s carries -2 v a s, which is not small."""
+    from oracle import ring
+    ctx = bfv.make_ctx(64, 2, T)
+    s, a, e, v, e0, e1, i = _rlwe_case(ctx, 5)
+    as_ = _schoolbook_limbs(ctx, a, s)
+    b_wrong = np.stack([(as_[l] + ring.reduce_signed(e, q)) % np.uint64(q) for l, q in enumerate(ctx.primes)])
+    c0 = bfv.encrypt_c0(ctx, i, v, e0, b_wrong)
+    assert (_decrypt_with_key(ctx, c0, a, s, v, e1) != (-i) % T).mean() > 0.9
+
+
+# ------------------------------------------------------------------ server evaluation by the schoolbook
+def _schoolbook_sum_of_products(ctx, l, xs, ys):
+    """sum_j xs[j] * ys[j, m] in Z_q[X]/(X^N+1) by the schoolbook definition."""
+    from oracle import ring
+    q = ctx.primes[l]
+    xs = np.asarray(xs)
+    ys = np.asarray(ys)
+    out = np.zeros(ys.shape[1:], dtype=np.uint64)
+    for j in range(xs.shape[0]):
+        for m in range(ys.shape[1]):
+            out[m] = (out[m] + ring.negacyclic_schoolbook(xs[j], ys[j, m], q)) % np.uint64(q)
+    return out
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 2, 2, 1), (3, 2, 2, 2, 2), (4, 4, 3, 2, 1)])
+def test_server_conv_equal_with_schoolbook_products(shape, monkeypatch):
+    """server_conv multiplies through the oracle's NTT; with every product taken by the schoolbook
+    definition instead (tiny N), the words of c0^r must be identical."""
+    c_i, c_o, H, W, stride = shape
+    N = 64
+    ctx = bfv.make_ctx(N, 2, T)
+    g = packing.conv_geometry(N, c_i, c_o, H, W, 3, stride, 1)
+    rng = np.random.default_rng(c_i * 10 + c_o)
+    F = rng.integers(-7, 8, (c_o, c_i, 3, 3))
+    fh = packing.pack_conv_filters(F, g)
+    rho = rng.integers(0, T, (g.K_in, c_o, N))
+    c0 = wl.uniform_per_modulus(rng, (g.K_in,), ctx.primes, N).astype(np.uint64)
+    sh = rng.integers(0, T, (g.K_in, N))
+    shn = rng.integers(0, T, (g.K_out, N))
+    ref = bfv.server_conv(ctx, g, c0, rho, fh, sh, shn)
+    monkeypatch.setattr(bfv, "_sum_of_products", _schoolbook_sum_of_products)
+    school = bfv.server_conv(ctx, g, c0, rho, fh, sh, shn)
+    assert (school == ref).all()
+
+
+@pytest.mark.parametrize("n_i,n_o,N", [(4, 2, 8), (6, 5, 64), (16, 10, 64)])
+def test_server_fc_equal_with_schoolbook_products(n_i, n_o, N, monkeypatch):
+    """As above for server_fc, including the Fig. 5 shape (n_i = 4, n_o = 2, N = 8)."""
+    ctx = bfv.make_ctx(N, 2, T)
+    g = packing.fc_geometry(N, n_i, n_o)
+    rng = np.random.default_rng(n_i * n_o + N)
+    w = packing.pack_fc_weights(rng.integers(-7, 8, (n_o, n_i)), g)
+    d = packing.pack_fc_bias(rng.integers(-7, 8, n_o), g)
+    rho = rng.integers(0, T, (g.blocks, N))
+    c0 = wl.uniform_per_modulus(rng, (), ctx.primes, N).astype(np.uint64)
+    sh = rng.integers(0, T, N)
+    shn = rng.integers(0, T, (g.blocks, g.n_o_p))
+    ref = bfv.server_fc(ctx, g, c0, rho, w, d, sh, shn)
+    monkeypatch.setattr(bfv, "_sum_of_products", _schoolbook_sum_of_products)
+    school = bfv.server_fc(ctx, g, c0, rho, w, d, sh, shn)
+    assert (school == ref).all()
