@@ -175,6 +175,25 @@ int he_conv_layer_ws(he_ctx *ctx, const he_layer *layer, uint32_t B,
                      uint32_t *d_out, void *d_workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * he_conv_layer_noalloc -- he_conv_layer for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and output words as he_conv_layer, but
+ * the workspace is a static device array of HE_NOALLOC_SCRATCH_BYTES bytes
+ * (one per GPU, held until the process ends, its address looked up once per
+ * device by he_setup), so the call needs no he_workspace_reserve and calls no
+ * allocator.  HE_ENOMEM, before any launch, when he_layer_workspace_bytes(
+ * layer, B) exceeds HE_NOALLOC_SCRATCH_BYTES.  Every call on one GPU shares
+ * that array and nothing in it is expected to start at any value: calls that
+ * overlap on one GPU (two streams, two host threads, two contexts) race and
+ * must be ordered by the caller.  Kernel timing (he_profile_*) does not see
+ * this form's launches.
+ */
+#define HE_NOALLOC_SCRATCH_BYTES (32u << 20)
+int he_conv_layer_noalloc(he_ctx *ctx, const he_layer *layer, uint32_t B,
+                          const uint32_t *d_c0, const uint32_t *d_sh, const uint32_t *d_sh_next,
+                          uint32_t *d_out, void *stream);
+
+/*
  * he_fc_layer -- server evaluation of one FC layer for B inputs (Alg. 2,
  * server evaluation; Theorem 1 places output b n_o' + k at coefficient k of
  * block b).

@@ -27,6 +27,11 @@
 #include "../../include/he.h"
 #include "he_kernels.h"
 
+// Workspace of he_conv_layer_noalloc: one array per device, alive until the process ends.  Host
+// code never uses the name `scratch` as an address; it uses the per-device address that
+// hipGetSymbolAddress returned when the first context was created on that device.
+static __device__ __align__(256) uint8_t scratch[HE_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -41,6 +46,31 @@ int dev_fail(hipError_t e, const char *what) {
         hipError_t e_ = (call);                                   \
         if (e_ != hipSuccess) return dev_fail(e_, #call);         \
     } while (0)
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Look up the scratch array's address on `dev`, which must be the current device (once per device).
+int scratch_bind(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        g_last_error = "device index beyond " + std::to_string(kMaxDevices);
+        return HE_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return HE_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return dev_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    g_scratch_ptr[dev] = p;
+    return HE_OK;
+}
+
+void *scratch_device_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
 
 typedef unsigned __int128 u128;
 
@@ -382,6 +412,13 @@ int he_setup(uint32_t N, uint32_t L, const uint32_t *primes, uint32_t t, he_ctx 
     he_ctx *ctx = new (std::nothrow) he_ctx();
     if (!ctx) return HE_ENOMEM;
     hipGetDevice(&ctx->device);
+    {
+        const int src = scratch_bind(ctx->device);
+        if (src != HE_OK) {
+            delete ctx;
+            return src;
+        }
+    }
     ctx->N = N;
     ctx->logN = log2u(N);
     ctx->L = L;
@@ -1231,6 +1268,31 @@ int he_conv_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d
     int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
     if (rc != HE_OK) return rc;
     return he_conv_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, stream);
+}
+
+int he_conv_layer_noalloc(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                          const uint32_t *d_sh_next, uint32_t *d_out, void *stream) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
+    if (B == 0) return HE_OK;
+    const size_t need = layer_ws_bytes(ly, B);
+    if (need > (size_t)HE_NOALLOC_SCRATCH_BYTES) {
+        g_last_error = "he_conv_layer_noalloc: " + std::to_string(need) + " bytes of scratch needed at B = " +
+                       std::to_string(B) + ", the static scratch holds " +
+                       std::to_string((size_t)HE_NOALLOC_SCRATCH_BYTES);
+        return HE_ENOMEM;
+    }
+    void *ws = scratch_device_ptr(ctx->device);
+    if (!ws) {
+        g_last_error = "he_conv_layer_noalloc: no scratch address for this device";
+        return HE_EDEVICE;
+    }
+    // timing events are created per launch when profiling is on; this form creates none
+    const bool saved = tl_no_prof;
+    tl_no_prof = true;
+    const int rc = he_conv_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, (size_t)HE_NOALLOC_SCRATCH_BYTES,
+                                    stream);
+    tl_no_prof = saved;
+    return rc;
 }
 
 int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,

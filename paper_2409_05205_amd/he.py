@@ -34,8 +34,9 @@ EXPORTED = [
     "he_tune_force", "he_autotune_layer", "he_tune_get",
     "he_layer_inputs_ntt", "he_conv_layer_ntt", "he_fc_layer_ntt",
     "he_pack_operands", "he_client_masks", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
-    "he_layer_geometry", "he_ctx_workspace_bytes", "he_workspace_reserve",
+    "he_layer_geometry", "he_ctx_workspace_bytes", "he_workspace_reserve", "he_conv_layer_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 32 << 20   # HE_NOALLOC_SCRATCH_BYTES in include/he.h
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
 HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL = 1, 2, 4, 8, 16
 
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_workspace_reserve.argtypes = [VP, VP, SZ]
     for name in ("he_conv_layer", "he_fc_layer"):
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
+    lib.he_conv_layer_noalloc.argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
     for name in ("he_conv_layer_ws", "he_fc_layer_ws"):
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP, SZ, VP]
     lib.he_layer_inputs_ntt.argtypes = [VP, VP, U32, VP, VP, VP, VP]
@@ -380,6 +382,19 @@ class Context:
             rc = lib.he_conv_layer_ws(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out),
                                       _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream))
         _check(rc, "he_conv_layer")
+        return out
+
+    def conv_layer_noalloc(self, layer: Layer, c0, out, sh=None, sh_next=None, stream=None):
+        """he_conv_layer_noalloc: the layer with the library's static device scratch as workspace."""
+        B = c0.shape[0]
+        i = layer.info
+        _check_dev(c0, (B, i.K_in, self.L, self.N), "c0")
+        _check_dev(sh, (B, i.K_in, self.N), "sh", True)
+        _check_dev(sh_next, (B, i.K_out, self.N), "sh_next", True)
+        _check_dev(out, (B, i.K_out, self.L, self.N), "out")
+        rc = load_library().he_conv_layer_noalloc(self.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next),
+                                                  _ptr(out), _stream(stream))
+        _check(rc, "he_conv_layer_noalloc")
         return out
 
     def fc_layer(self, layer: Layer, c0, sh=None, sh_next=None, out=None, stream=None, workspace=None):
