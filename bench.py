@@ -164,11 +164,12 @@ class Stack:
         return sum(B for _, B, _, _, _ in self.steps)
 
     def mac_plan(self, he):
-        """Which launch carries each layer's MAC: 'fused' (MAC + residue-class tail in one
-        launch) or 'split' (MAC launch, then tail / inverse launch), read from the kernel
-        kinds one call of the layer records."""
+        """Which launch carries each layer's MAC: 'one' (the whole layer in one launch), 'fused'
+        (MAC + residue-class tail in one launch, after a forward-transform launch) or 'split' (MAC
+        launch, then tail / inverse launch), read from the kernel kinds one call of the layer
+        records."""
         plan = []
-        kinds = he.HE_K_MAC | he.HE_K_MAC_TAIL
+        kinds = he.HE_K_MAC | he.HE_K_MAC_TAIL | he.HE_K_LAYER
         for ly, B, c0, sh, shn in self.steps:
             self.ctx.profile_reset()
             self.ctx.profile_enable(kinds)
@@ -176,19 +177,22 @@ class Stack:
                 self.ctx.conv_layer(ly, c0, sh, shn)
             else:
                 self.ctx.fc_layer(ly, c0, sh, shn)
+            one = self.ctx.profile_read(he.HE_K_LAYER)[0] > 0
             fused = self.ctx.profile_read(he.HE_K_MAC_TAIL)[0] > 0
             self.ctx.profile_enable(0)
-            plan.append("fused" if fused else "split")
+            plan.append("one" if one else ("fused" if fused else "split"))
         self.ctx.profile_reset()
         return plan
 
-    def mac_kernel_bytes(self, plan):
+    def mac_kernel_bytes(self, plan, only=None):
         """Algorithmic bytes of the launches that carry the MAC in one pass: resident operand
         rows once, NTT-domain inputs once per image, and what the launch writes (block sums or
         products for a split MAC; output polynomials, after reading sh', for a fused one)."""
         tot = 0
         L, N = self.ctx.L, self.ctx.N
-        for (ly, B, c0, sh, shn), c_o, form in zip(self.steps, self.rows, plan):
+        for k, ((ly, B, c0, sh, shn), c_o, form) in enumerate(zip(self.steps, self.rows, plan)):
+            if only is not None and not only[k]:
+                continue
             i = ly.info
             J = i.K_in * (2 if sh is not None else 1)
             tot += J * c_o * L * N * 4 + B * J * L * N * 4
@@ -197,6 +201,25 @@ class Stack:
             else:
                 out_per = N // i.s if ly.kind == 0 and i.flags == 0 else N
                 tot += B * c_o * L * out_per * 4
+        return tot
+
+    def layer_bytes(self, only=None):
+        """Algorithmic HBM bytes of one pass of whole layer calls: c0, sh and sh' read, the resident
+        operand rows read once, the output polynomials (FC: their n_o' kept coefficients) written."""
+        L, N = self.ctx.L, self.ctx.N
+        tot = 0
+        for k, ((ly, B, c0, sh, shn), rows) in enumerate(zip(self.steps, self.rows)):
+            if only is not None and not only[k]:
+                continue
+            i = ly.info
+            J = i.K_in * (2 if sh is not None else 1)
+            tot += J * rows * L * N * 4 + B * i.K_in * L * N * 4
+            if sh is not None:
+                tot += B * i.K_in * N * 4
+            if ly.kind == 0:
+                tot += B * i.K_out * L * N * 4 + (B * i.K_out * N * 4 if shn is not None else 0)
+            else:
+                tot += B * rows * L * i.n_o_p * 4 + (B * rows * i.n_o_p * 4 if shn is not None else 0)
         return tot
 
     def fwd_bytes(self):
@@ -228,12 +251,14 @@ class Stack:
                 tot += B * rows * i.n_o_p * 4 if shn is not None else 0
         return tot
 
-    def butterflies_fwd(self):
+    def butterflies_fwd(self, only=None):
         """Forward-NTT butterflies of one pass (c0 rows, plus sh rows where present)."""
         L, N = self.ctx.L, self.ctx.N
         per_row = (N // 2) * (N.bit_length() - 1)
         tot = 0
-        for ly, B, c0, sh, shn in self.steps:
+        for k, (ly, B, c0, sh, shn) in enumerate(self.steps):
+            if only is not None and not only[k]:
+                continue
             tot += B * ly.info.K_in * L * (2 if sh is not None else 1) * per_row
         return tot
 
@@ -502,9 +527,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="also run one 256 MiB device-to-device copy (known bytes) for counter calibration")
-    ap.add_argument("--pmc-mac-form", choices=["F", "S"], default=None,
+    ap.add_argument("--pmc-mac-form", choices=["F", "S", "O"], default=None,
                     help="counter runs: pin every layer of the plain stack to the fused (F) or split (S) MAC "
-                         "form, run only the plain loop and print the plan (the per-layer traffic table)")
+                         "form or the one-launch layer (O), run only the plain loop and print the plan (the "
+                         "per-layer traffic table)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards across GPUs by "
@@ -525,7 +551,7 @@ def main():
     st = Stack(he, ctx, wl.CONFIG_PLAIN20_X1, 1, [10], [1], 8192, 4)
     n_layers = len(st.steps)
     if args.pmc_mac_form is not None:
-        ctx.tune_force(he.HE_TUNE_MAC, 2 if args.pmc_mac_form == "F" else 0)
+        ctx.tune_force(he.HE_TUNE_MAC, {"F": 2, "S": 0, "O": 7}[args.pmc_mac_form])
     elif not args.no_tune:
         st.autotune()
     sync()
@@ -543,7 +569,7 @@ def main():
     log(f"plain: {T_plain / args.steps * 1e3:.3f} ms/step")
     if args.pmc_mac_form is not None:
         # layer order of the MAC launches above is the stack order, one per layer per call
-        plan = "".join("F" if p == "fused" else "S" for p in st.mac_plan(he))
+        plan = "".join({"one": "O", "fused": "F", "split": "S"}[p] for p in st.mac_plan(he))
         print(json.dumps({"pmc_mac_form": args.pmc_mac_form, "plan": plan,
                           "calls": args.warmup + args.steps + 1}), flush=True)
         return
@@ -551,12 +577,12 @@ def main():
     # kernel timing of the same calls (HIP events on the launch stream)
     plan = st.mac_plan(he)
     ctx.profile_reset()
-    ctx.profile_enable(he.HE_K_MAC | he.HE_K_NTT_FWD | he.HE_K_TAIL | he.HE_K_INTT | he.HE_K_MAC_TAIL)
+    ctx.profile_enable(he.HE_K_MAC | he.HE_K_NTT_FWD | he.HE_K_TAIL | he.HE_K_INTT | he.HE_K_MAC_TAIL | he.HE_K_LAYER)
     with torch.cuda.stream(stream):
         T_prof = time_loop(lambda: st.seq.run(stream), args.steps, 0, sync)
     kern = {}
     for name, kind in [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL),
-                       ("intt", he.HE_K_INTT), ("mac_tail", he.HE_K_MAC_TAIL)]:
+                       ("intt", he.HE_K_INTT), ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER)]:
         n, ms = ctx.profile_read(kind)
         kern[name] = {"launches": n, "total_ms": ms, "avg_us": (ms * 1e3 / n) if n else None}
     ctx.profile_enable(0)
@@ -598,32 +624,54 @@ def main():
 
     # the launches that carry the MAC: fused MAC + tail (conv layers at batch one) and the
     # split MAC (FC head, and any layer the tuner gave the two-launch form)
-    mac_bytes = st.mac_kernel_bytes(plan)
-    mac_launches_per_step = n_layers
-    mac_ms = kern["mac"]["total_ms"] + kern["mac_tail"]["total_ms"]
+    rooflines = {}
+    per_step = {}
+    plan_letters = "".join({"one": "O", "fused": "F", "split": "S"}[p] for p in plan)
+    n_one = plan.count("one")
+    if kern["layer"]["launches"]:
+        # whole layers in one launch (forward transforms, MAC, inverse, extraction)
+        one_bytes = st.layer_bytes(only=[p == "one" for p in plan])
+        lay_avg_s = kern["layer"]["total_ms"] / 1e3 / kern["layer"]["launches"]
+        ach = one_bytes / n_one / lay_avg_s / 1e9
+        rooflines["layer"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("layer", plan_letters),
+                              "algorithmic_bytes_per_launch": one_bytes // n_one,
+                              "kernel": f"k_fused_layer (forward NTT, MAC, residue-class / prefix inverse and "
+                                        f"extraction in one launch, {n_one} layers)",
+                              "launches_per_step": n_one, "avg_launch_us": round(lay_avg_s * 1e6, 3)}
+        per_step["layer"] = kern["layer"]["total_ms"]
     mac_n = kern["mac"]["launches"] + kern["mac_tail"]["launches"]
-    mac_avg_s = mac_ms / 1e3 / mac_n
-    achieved = mac_bytes / mac_launches_per_step / mac_avg_s / 1e9
-    n_fused = plan.count("fused")
-    plan_letters = "".join("F" if p == "fused" else "S" for p in plan)
-    roof_mac = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": pmc_traffic("mac", plan_letters), "mac_forms": plan_letters,
-                "algorithmic_bytes_per_launch": mac_bytes // mac_launches_per_step,
-                "kernel": f"k_mac_tail (fused MAC + residue-class inverse, {n_fused} layers) / "
-                          f"k_mac_class, k_mac_full (split MAC, {n_layers - n_fused} layers)",
-                "launches_per_step": mac_launches_per_step, "avg_launch_us": round(mac_avg_s * 1e6, 3)}
-    fwd_avg_s = kern["ntt_fwd"]["total_ms"] / 1e3 / kern["ntt_fwd"]["launches"]
-    fwd_bfly = st.butterflies_fwd() / n_layers          # one forward launch per layer
-    fwd_g = fwd_bfly / fwd_avg_s / 1e9
-    roof_fwd = {"bound": "alu", "achieved": round(fwd_g, 1), "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s",
-                "frac": round(fwd_g / BFLY_PEAK_G, 4), "traffic": pmc_traffic("ntt_fwd"),
-                "butterflies_per_launch": int(fwd_bfly), "kernel": "k_ntt_fwd (forward negacyclic NTT)",
-                "launches_per_step": n_layers, "avg_launch_us": round(fwd_avg_s * 1e6, 3)}
-    per_step = {"ntt_fwd": kern["ntt_fwd"]["total_ms"], "mac": mac_ms,
-                "tail": kern["tail"]["total_ms"] + kern["intt"]["total_ms"]}
+    if mac_n:
+        multi = [p != "one" for p in plan]
+        n_multi = sum(multi)
+        mac_bytes = st.mac_kernel_bytes(plan, only=multi)
+        mac_ms = kern["mac"]["total_ms"] + kern["mac_tail"]["total_ms"]
+        mac_avg_s = mac_ms / 1e3 / mac_n
+        achieved = mac_bytes / n_multi / mac_avg_s / 1e9
+        n_fused = plan.count("fused")
+        rooflines["mac"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(achieved / HBM_PEAK_GBS, 4),
+                            "traffic": pmc_traffic("mac", plan_letters), "mac_forms": plan_letters,
+                            "algorithmic_bytes_per_launch": mac_bytes // n_multi,
+                            "kernel": f"k_mac_tail (fused MAC + residue-class inverse, {n_fused} layers) / "
+                                      f"k_mac_class, k_mac_full (split MAC, {n_multi - n_fused} layers)",
+                            "launches_per_step": n_multi, "avg_launch_us": round(mac_avg_s * 1e6, 3)}
+        per_step["mac"] = mac_ms
+    if kern["ntt_fwd"]["launches"]:
+        multi = [p != "one" for p in plan]
+        fwd_avg_s = kern["ntt_fwd"]["total_ms"] / 1e3 / kern["ntt_fwd"]["launches"]
+        fwd_bfly = st.butterflies_fwd(only=multi) / sum(multi)        # one forward launch per layer
+        fwd_g = fwd_bfly / fwd_avg_s / 1e9
+        rooflines["ntt_fwd"] = {"bound": "alu", "achieved": round(fwd_g, 1), "peak": BFLY_PEAK_G,
+                                "unit": "Gbutterfly/s", "frac": round(fwd_g / BFLY_PEAK_G, 4),
+                                "traffic": pmc_traffic("ntt_fwd"), "butterflies_per_launch": int(fwd_bfly),
+                                "kernel": "k_ntt_fwd (forward negacyclic NTT)", "launches_per_step": sum(multi),
+                                "avg_launch_us": round(fwd_avg_s * 1e6, 3)}
+        per_step["ntt_fwd"] = kern["ntt_fwd"]["total_ms"]
+    if kern["tail"]["launches"] + kern["intt"]["launches"]:
+        per_step["tail"] = kern["tail"]["total_ms"] + kern["intt"]["total_ms"]
     dominant = max(per_step, key=per_step.get)
-    roofline = roof_fwd if dominant == "ntt_fwd" else roof_mac
+    roofline = rooflines.get(dominant) or rooflines.get("mac") or rooflines["layer"]
     layers_per_s = n_layers * args.steps / T_plain
     graph_lps = n_layers * args.steps / T_graph
     result = {
@@ -644,7 +692,8 @@ def main():
                    "form": "plain: native runtime issues the 20 layer calls back to back on one stream"},
         "limb_poly_macs_per_s": round(st.modmuls() / 8192 * args.steps / T_plain, 1),
         "roofline": roofline,
-        "rooflines": {"mac": roof_mac, "ntt_fwd": roof_fwd},
+        "rooflines": rooflines,
+        "layer_forms": plan_letters,
         "dominant_kernel": dominant,
         "kernels": kern,
         "forms": {

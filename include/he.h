@@ -141,7 +141,9 @@ size_t he_ctx_workspace_bytes(const he_ctx *ctx, uint32_t rows);
 /*
  * he_workspace_reserve -- make the context-owned workspace of `stream` at
  * least `bytes` bytes (he_layer_workspace_bytes / he_ctx_workspace_bytes give
- * the sizes).  The calls that use a context workspace (he_conv_layer,
+ * the sizes), and give the stream the 64 KiB counter block that the one-launch
+ * layer form needs (created zeroed on the first reservation; every launch
+ * leaves it zero).  The calls that use a context workspace (he_conv_layer,
  * he_fc_layer, he_conv_layer_ntt, he_fc_layer_ntt, he_encrypt_c0,
  * he_poly_mul) never allocate: they fail with HE_ENOMEM, before any launch,
  * when the stream's reserved workspace is smaller than they need.  Growing a
@@ -151,6 +153,16 @@ size_t he_ctx_workspace_bytes(const he_ctx *ctx, uint32_t rows);
  * different streams need their own reservations.
  */
 int he_workspace_reserve(he_ctx *ctx, void *stream, size_t bytes);
+
+/*
+ * he_sync_check -- HE_EDEVICE if a one-launch layer call that used the counter
+ * block of `stream` (its he_workspace_reserve reservation) gave up a bounded
+ * wait for a work item it depends on (its output words are then undefined;
+ * the flag is cleared), else HE_OK.  Synchronises the stream.  Each wait
+ * depends only on items that started earlier in the same launch, so a wait
+ * ends unless the device stalls for about a second.
+ */
+int he_sync_check(he_ctx *ctx, void *stream);
 
 /*
  * he_conv_layer -- server evaluation of one Conv layer for B images
@@ -256,9 +268,11 @@ int he_poly_mul(he_ctx *ctx, uint32_t rows, const uint32_t *d_a, const uint32_t 
  * events and returns the number of launches and their summed duration (ms)
  * since the last reset.  Kinds: HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL (residue-
  * class inverse + extraction), HE_K_INTT (full inverse + extraction),
- * HE_K_MAC_TAIL (MAC, residue-class inverse and extraction in one launch).
+ * HE_K_MAC_TAIL (MAC, residue-class inverse and extraction in one launch),
+ * HE_K_LAYER (the whole layer in one launch: forward transforms, MAC, inverse
+ * and extraction).
  */
-enum { HE_K_NTT_FWD = 1, HE_K_MAC = 2, HE_K_TAIL = 4, HE_K_INTT = 8, HE_K_MAC_TAIL = 16 };
+enum { HE_K_NTT_FWD = 1, HE_K_MAC = 2, HE_K_TAIL = 4, HE_K_INTT = 8, HE_K_MAC_TAIL = 16, HE_K_LAYER = 32 };
 int he_profile_enable(he_ctx *ctx, uint32_t kind_mask);
 int he_profile_read(he_ctx *ctx, uint32_t kind, uint64_t *launches, double *total_ms);
 int he_profile_reset(he_ctx *ctx);
@@ -377,10 +391,20 @@ void he_server_free(he_server *srv);
  * and extraction fused, one workgroup per output row), 3 (residue-class conv
  * layers, B >= 2: LDS-staged batched MAC over image x channel tiles), 4 (as
  * 3, with neighbouring tiles on one XCD), 5 and 6 (as 3 and 4, each stage
- * moved from memory to LDS by DMA, three stages in flight) or -1
- * (automatic: 2 at B = 1, except 0 for layers with K_in >= 2 and at most 64
- * output rows K_out g_o L; at B >= 4, 5 for residue-class layers and 1 for
- * full-length ones); a value the layer's shape does not allow falls back to 0.  Every value yields the same output words.  he_tune_force pins a knob for the whole context (tests
+ * moved from memory to LDS by DMA, three stages in flight), 7 (conv and FC:
+ * the whole layer in one launch, forward transforms included, work items in
+ * workgroup order that wait on counters), 8 (conv: one launch of whole-row
+ * transforms and one MAC + inverse item per output row) or -1 (automatic:
+ * 7 for FC layers at B = 1 where the shape allows it (N 4096..16384,
+ * n_o' <= 1024); for conv layers at B = 1, 2, except 0 for layers with
+ * K_in >= 2 and at most 64 output rows K_out g_o L; at B >= 4, 5 for
+ * residue-class layers and 1 for full-length ones).  The one-launch forms need
+ * a counter block: the calls that use a reserved stream workspace,
+ * he_conv_layer_noalloc, layer sequences and the server have one, a *_ws call
+ * has one when its stream has a reservation; otherwise, and for a shape a
+ * form does not allow, the automatic multi-launch form runs.  Every value
+ * yields the same output words.
+ * he_tune_force pins a knob for the whole context (tests
  * sweep all values with it).  he_autotune_layer tunes the knobs of one layer at
  * batch B one after another: each candidate is timed as a whole layer call on
  * scratch buffers (median of 5, caches evicted before each), and the fastest is

@@ -25,12 +25,15 @@
 #include <vector>
 
 #include "../../include/he.h"
+#include "he_internal.h"
 #include "he_kernels.h"
 
 // Workspace of he_conv_layer_noalloc: one array per device, alive until the process ends.  Host
 // code never uses the name `scratch` as an address; it uses the per-device address that
 // hipGetSymbolAddress returned when the first context was created on that device.
-static __device__ __align__(256) uint8_t scratch[HE_NOALLOC_SCRATCH_BYTES];
+// The sync block of the one-launch layer form follows the workspace part (zero at load; every
+// launch leaves it zero).
+static __device__ __align__(256) uint8_t scratch[HE_NOALLOC_SCRATCH_BYTES + FZ_SYNC_WORDS * 4];
 
 namespace {
 
@@ -139,6 +142,7 @@ uint32_t pow2_floor(uint32_t x) {
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
+    uint32_t *sync = nullptr;   // zeroed counter block of the one-launch layer form (FZ_SYNC_WORDS words)
 };
 
 struct ProfRec {
@@ -191,7 +195,7 @@ size_t layer_ws_bytes(const he_layer *ly, uint32_t B) {
 
 // The workspace reserved for `st` (he_workspace_reserve); a call never allocates.  Fails with
 // HE_ENOMEM, naming the bytes needed, when nothing or too little was reserved for the stream.
-int ctx_workspace(he_ctx *ctx, hipStream_t st, size_t bytes, void **out) {
+int ctx_workspace(he_ctx *ctx, hipStream_t st, size_t bytes, void **out, uint32_t **sync = nullptr) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto it = ctx->ws.find(st);
     if (it == ctx->ws.end() || it->second.bytes < bytes) {
@@ -201,7 +205,15 @@ int ctx_workspace(he_ctx *ctx, hipStream_t st, size_t bytes, void **out) {
         return HE_ENOMEM;
     }
     *out = it->second.ptr;
+    if (sync) *sync = it->second.sync;
     return HE_OK;
+}
+
+// The sync block reserved for `st` (he_workspace_reserve), or null.
+uint32_t *ctx_sync(he_ctx *ctx, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->ws.find(st);
+    return it == ctx->ws.end() ? nullptr : it->second.sync;
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -266,9 +278,37 @@ bool mac_lds_ok(const he_layer *ly, uint32_t B) {
     return B >= 2 && in.kind == HE_LAYER_CONV && in.flags == HE_PACK_CLASS_INTT && in.s >= 2 && in.N >= 256;
 }
 
-int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
-    int mk = ctx->force_mac;
-    if (mk < 0) mk = mac_tuned(ctx, ly, B);
+// The one-launch layer form (kernels_fused.hip) for this layer at batch B: its item geometry
+// in *jb when the shape allows it.  Its MAC reads the resident operands once per image, so
+// the automatic rule keeps it for B = 1.
+bool layer_one_launch_ok(const he_ctx *ctx, const he_layer *ly, uint32_t B, FusedLayer *jb, bool rows = false) {
+    const he_layer_info &in = ly->info;
+    FusedLayer f;
+    std::memset(&f, 0, sizeof(f));
+    f.kind = in.kind == HE_LAYER_CONV ? FZ_KIND_CONV : FZ_KIND_FC;
+    if (in.kind == HE_LAYER_CONV && in.flags != HE_PACK_CLASS_INTT) return false;
+    f.B = B;
+    f.K_in = in.K_in;
+    f.Jtot = 2 * in.K_in;
+    f.Juse = f.Jtot;
+    f.rows = ly->n_rows;
+    f.g_o = in.g_o;
+    f.K_out = in.K_out;
+    f.L = in.L;
+    f.logN = ctx->logN;
+    f.s_log = in.kind == HE_LAYER_CONV ? log2u(in.s) : 0;
+    f.n_o_p = in.n_o_p;
+    f.rows_form = rows ? 1u : 0u;
+    if (!fused_layer_ok(f)) return false;
+    f.ntt_c0 = f.ntt_sh = in.K_in;
+    if (FZ_SB_HDR + fused_layer_plan(f) > FZ_SYNC_WORDS) return false;
+    if (jb) *jb = f;
+    return true;
+}
+
+// The multi-launch MAC form of a conv layer (values 0..6) for a forced or tuned value mk (-1:
+// the automatic rule).
+int mac_variant_multi(he_ctx *ctx, const he_layer *ly, uint32_t B, int mk) {
     const bool tiled_ok = mac_tiled_ok(ly, B), fused_ok = mac_fused_ok(ctx, ly);
     if (mk == 3 || mk == 4 || mk == 5 || mk == 6) return mac_lds_ok(ly, B) ? mk : 0;
     if (mk == 2) return fused_ok ? 2 : 0;
@@ -283,6 +323,22 @@ int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
     }
     if (B >= 4 && mac_lds_ok(ly, B)) return 5;
     return tiled_ok && B >= 4 ? 1 : 0;
+}
+
+// The form of a layer call at batch B: 7 = the one-launch layer (conv or FC; by default for an FC
+// layer at B = 1 when the shape allows it), 8 = the one-launch conv layer with one MAC + inverse
+// item per output row, else the multi-launch MAC form of a conv layer (0..6), -1 for the
+// multi-launch FC.  For conv layers at B = 1 the automatic rule keeps the multi-launch forms: a
+// hand-over between workgroups inside a launch costs about as much as a launch boundary on this
+// device, and the forward transforms slow down under the overlapped operand stream.
+int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
+    int mk = ctx->force_mac;
+    if (mk < 0) mk = mac_tuned(ctx, ly, B);
+    const bool conv = ly->info.kind == HE_LAYER_CONV;
+    if (mk == 8 && layer_one_launch_ok(ctx, ly, B, nullptr, true)) return 8;
+    if ((mk == 7 || mk == 8 || (mk < 0 && B == 1 && !conv)) && layer_one_launch_ok(ctx, ly, B, nullptr)) return 7;
+    if (!conv) return -1;
+    return mac_variant_multi(ctx, ly, B, mk >= 7 ? -1 : mk);
 }
 
 // Times one kernel launch with dispatch-recorded events when profiling is on for its kind.
@@ -538,7 +594,8 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
     const size_t out_b = align256(conv ? (size_t)B * in.K_out * L * N * 4 : (size_t)B * in.blocks * L * in.n_o_p * 4);
     const size_t ws_b = align256(layer_ws_bytes(ly, B));
     const size_t flush_b = (size_t)512 << 20;
-    const size_t data_b = c0_b + sh_b + shn_b + out_b + ws_b;
+    const size_t sync_b = (size_t)FZ_SYNC_WORDS * 4;   // the trials' own counter block (zeroed below)
+    const size_t data_b = c0_b + sh_b + shn_b + out_b + ws_b + sync_b;
     char *buf = nullptr;
     if (hipMalloc((void **)&buf, data_b + flush_b) != hipSuccess) return HE_ENOMEM;
     const uint32_t *c0 = (const uint32_t *)buf;
@@ -546,6 +603,7 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
     const uint32_t *shn = (const uint32_t *)(buf + c0_b + sh_b);
     uint32_t *out = (uint32_t *)(buf + c0_b + sh_b + shn_b);
     void *ws = buf + c0_b + sh_b + shn_b + out_b;
+    uint32_t *tsync = (uint32_t *)(buf + c0_b + sh_b + shn_b + out_b + ws_b);
     char *flush = buf + data_b;
     hipEvent_t ea = nullptr, eb = nullptr;
     int rc = HE_OK;
@@ -566,8 +624,7 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         for (int r = -1; r < REPS; ++r) {
             if (hipMemsetAsync(flush, r & 0xff, flush_b, st) != hipSuccess) return HE_EDEVICE;
             if (hipEventRecord(ea, st) != hipSuccess) return HE_EDEVICE;
-            const int lrc = conv ? he_conv_layer_ws(ctx, ly, B, c0, with_sh ? sh : nullptr, shn, out, ws, ws_b, st)
-                                 : he_fc_layer_ws(ctx, ly, B, c0, with_sh ? sh : nullptr, shn, out, ws, ws_b, st);
+            const int lrc = he_layer_call_sync(ctx, ly, B, c0, with_sh ? sh : nullptr, shn, out, ws, ws_b, tsync, st);
             if (lrc != HE_OK) return lrc;
             if (hipEventRecord(eb, st) != hipSuccess || hipEventSynchronize(eb) != hipSuccess) return HE_EDEVICE;
             if (r >= 0 && hipEventElapsedTime(&ms[r], ea, eb) != hipSuccess) return HE_EDEVICE;
@@ -607,9 +664,14 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
     int chosen = 0;
     const std::vector<int> radix{2, 3, 4, 5};
     const uint32_t fwd_rows = (conv ? B * in.K_in : B) * L;
-    // a network's first layer has no input share: its forward launch has half the rows
+    // the forward launch's radix is timed under a multi-launch form (a one-launch layer has its own
+    // forward items); a network's first layer has no input share: its forward launch has half the rows
+    trial.mac_layer = ly;
+    trial.mac_B = B;
+    trial.mac = conv ? mac_variant_multi(ctx, ly, B, -1) : 0;
     if (rc == HE_OK) rc = pick(knob_setter(HE_TUNE_NTT_FWD, logN, fwd_rows), radix, false, &chosen);
     if (rc == HE_OK) rc = pick(knob_setter(HE_TUNE_NTT_FWD, logN, 2 * fwd_rows), radix, true, &chosen);
+    trial.mac = -2;
     bool mac_done = false;
     int mac_pick = -1;
     if (conv) {
@@ -623,6 +685,8 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         if (mac_fused_ok(ctx, ly)) macs.push_back(2);
         if (mac_lds_ok(ly, B))
             for (int m : {3, 4, 5, 6}) macs.push_back(m);
+        if (layer_one_launch_ok(ctx, ly, B, nullptr)) macs.push_back(7);
+        if (layer_one_launch_ok(ctx, ly, B, nullptr, true)) macs.push_back(8);
         trial.mac_layer = ly;
         trial.mac_B = B;
         trial.mac = -1;   // the automatic rule while the other knobs are tuned
@@ -632,7 +696,8 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         // inverse), so that the MAC forms below are compared against a tuned tail; its key is
         // shared by the layers of one shape, and the first of them would otherwise see the default
         if (rc == HE_OK && cls && logm >= 4) {
-            if (mac_variant(ctx, ly, B) == 2) trial.mac = 0;
+            const int mv = mac_variant(ctx, ly, B);
+            if (mv == 2 || mv >= 7) trial.mac = 0;
             rc = pick(knob_setter(HE_TUNE_TAIL, logm, rows), radix, true, &chosen);
             trial.mac = -1;
         }
@@ -643,7 +708,17 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         }
         if (rc == HE_OK && !cls) rc = pick(knob_setter(HE_TUNE_NTT_INV, logN, rows), radix, true, &chosen);
     } else if (rc == HE_OK) {
+        // FC: the multi-launch form's inverse radix, then that form against the one-launch form
+        trial.mac_layer = ly;
+        trial.mac_B = B;
+        trial.mac = 0;
         rc = pick(knob_setter(HE_TUNE_NTT_INV, logN, B * in.blocks * L), radix, true, &chosen);
+        if (rc == HE_OK && layer_one_launch_ok(ctx, ly, B, nullptr)) {
+            trial.mac = -1;
+            const int pref = mac_variant(ctx, ly, B) == 7 ? 7 : 0;
+            rc = pick([&trial](int c) { trial.mac = c; }, std::vector<int>{0, 7}, true, &mac_pick, pref, 0.05);
+            mac_done = rc == HE_OK;
+        }
     }
     tl_trial = saved_trial;
     tl_no_prof = saved_noprof;
@@ -712,8 +787,10 @@ void he_free(he_ctx *ctx) {
     hipFree(ctx->twi);
     hipFree(ctx->twish);
     hipFree(ctx->xinv);
-    for (auto &kv : ctx->ws)
+    for (auto &kv : ctx->ws) {
         if (kv.second.ptr) hipFree(kv.second.ptr);
+        if (kv.second.sync) hipFree(kv.second.sync);
+    }
     delete ctx;
 }
 
@@ -753,11 +830,35 @@ size_t he_ctx_workspace_bytes(const he_ctx *ctx, uint32_t rows) {
     return enc > mul ? enc : mul;
 }
 
+int he_sync_check(he_ctx *ctx, void *stream) {
+    if (!ctx) return HE_EINVAL;
+    uint32_t *sync = ctx_sync(ctx, (hipStream_t)stream);
+    if (!sync) return HE_OK;
+    HE_HIP(hipStreamSynchronize((hipStream_t)stream));
+    uint32_t err = 0;
+    HE_HIP(hipMemcpy(&err, sync + FZ_SB_ERR, 4, hipMemcpyDeviceToHost));
+    if (err == 0) return HE_OK;
+    HE_HIP(hipMemset(sync + FZ_SB_ERR, 0, 4));
+    g_last_error = "a one-launch layer call on this stream gave up waiting for an item it depends on";
+    return HE_EDEVICE;
+}
+
 int he_workspace_reserve(he_ctx *ctx, void *stream, size_t bytes) {
     if (!ctx) return HE_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(ctx->mu);
     Workspace &w = ctx->ws[st];
+    if (!w.sync) {
+        // counters of the one-launch layer form: zero now, and zero again after every launch
+        hipError_t e = hipMalloc((void **)&w.sync, (size_t)FZ_SYNC_WORDS * 4);
+        if (e == hipSuccess) e = hipMemset(w.sync, 0, (size_t)FZ_SYNC_WORDS * 4);
+        if (e != hipSuccess) {
+            if (w.sync) hipFree(w.sync);
+            w.sync = nullptr;
+            g_last_error = std::string("sync block: ") + hipGetErrorString(e);
+            return HE_ENOMEM;
+        }
+    }
     if (w.bytes >= bytes) return HE_OK;
     // the old buffer may still be read by work queued on any stream: let it drain first
     if (w.ptr) {
@@ -1152,7 +1253,8 @@ int conv_from_x(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *xn,
     // a2: coefficient-wise MAC over the input rows
     const uint32_t Juse = has_sh ? Jtot : K_in;
     const bool cls = in.flags == HE_PACK_CLASS_INTT;
-    const int mk = mac_variant(ctx, ly, B);
+    int mk = mac_variant(ctx, ly, B);
+    if (mk >= 7) mk = mac_variant_multi(ctx, ly, B, -1);   // no sync block here: the multi-launch rule
     if (mk == 2) {
         // a2 + a3 + a4 in one launch: MAC, residue-class inverse, extraction, + Delta sh'
         ProfScope ps(ctx, HE_K_MAC_TAIL);
@@ -1244,19 +1346,88 @@ int fc_from_x(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *xn, b
 
 }  // namespace
 
+}  // extern "C"
+
+namespace {
+
+// a1-a5 of one layer call.  x_given: NTT-domain inputs (the *_ntt forms; ws then holds only the
+// MAC output), else c0 / sh are transformed into ws.  sync: a zeroed sync block for the
+// one-launch form, or null for the multi-launch forms.
+int layer_exec(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+               const uint32_t *x_given, bool has_sh, const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws,
+               uint32_t *sync, hipStream_t st) {
+    const bool conv = ly->info.kind == HE_LAYER_CONV;
+    uint32_t *xn = x_given ? const_cast<uint32_t *>(x_given) : (uint32_t *)d_ws;
+    uint32_t *mac = x_given ? (uint32_t *)d_ws : (uint32_t *)((char *)d_ws + x_bytes(ly, B));
+    FusedLayer jb;
+    const int form = sync ? mac_variant(ctx, ly, B) : -1;
+    if ((form == 7 || form == 8) && layer_one_launch_ok(ctx, ly, B, &jb, form == 8)) {
+        jb.c0 = d_c0;
+        jb.sh = d_sh;
+        jb.sh_next = d_sh_next;
+        jb.out = d_out;
+        jb.op = ly->op;
+        jb.bias = ly->bias;
+        jb.x = xn;
+        jb.h = mac;
+        jb.Juse = has_sh ? jb.Jtot : jb.K_in;
+        jb.ntt_c0 = x_given ? 0 : jb.K_in;
+        jb.ntt_sh = (x_given || !d_sh) ? 0 : jb.K_in;
+        fused_layer_plan(jb);
+        ProfScope ps(ctx, HE_K_LAYER);
+        hipError_t e = launch_fused_layer(jb, ctx->tw, ctx->twsh, ctx->twi, ctx->twish, ctx->xinv, ctx->lc, sync,
+                                          st, ps.ev());
+        if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, conv ? "conv layer launch" : "fc layer launch");
+        return HE_OK;
+    }
+    if (!x_given) {
+        const hipError_t e = inputs_ntt(ctx, ly, B, d_c0, d_sh, xn, st);
+        if (e != hipSuccess) return dev_fail(e, conv ? "conv forward ntt" : "fc forward ntt");
+    }
+    return conv ? conv_from_x(ctx, ly, B, xn, has_sh, d_sh_next, d_out, mac, st)
+                : fc_from_x(ctx, ly, B, xn, has_sh, d_sh_next, d_out, mac, st);
+}
+
+int check_layer_args(const he_ctx *ctx, const he_layer *ly, int kind, const uint32_t *d_c0, const uint32_t *d_out,
+                     const void *d_ws) {
+    if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != kind) return HE_EINVAL;
+    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
+    if (!aligned16(d_c0) || !aligned16(d_ws)) return HE_EINVAL;
+    if (kind == HE_LAYER_CONV && !aligned16(d_out)) return HE_EINVAL;
+    return HE_OK;
+}
+
+}  // namespace
+
+int he_layer_call_sync(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
+                       const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, uint32_t *sync,
+                       void *stream) {
+    if (!ly) return HE_EINVAL;
+    if (B == 0) return (ctx && ly->ctx == ctx) ? HE_OK : HE_EINVAL;
+    const int rc = check_layer_args(ctx, ly, ly->info.kind, d_c0, d_out, d_ws);
+    if (rc != HE_OK) return rc;
+    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
+    return layer_exec(ctx, ly, B, d_c0, d_sh, nullptr, d_sh != nullptr, d_sh_next, d_out, d_ws, sync,
+                      (hipStream_t)stream);
+}
+
+uint32_t *he_sync_block_alloc() {
+    uint32_t *p = nullptr;
+    if (hipMalloc((void **)&p, (size_t)FZ_SYNC_WORDS * 4) != hipSuccess) return nullptr;
+    if (hipMemset(p, 0, (size_t)FZ_SYNC_WORDS * 4) != hipSuccess) {
+        hipFree(p);
+        return nullptr;
+    }
+    return p;
+}
+
+extern "C" {
+
 int he_conv_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
                      const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, void *stream) {
     if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
-    if (B == 0) return HE_OK;
-    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
-    if (!aligned16(d_c0) || !aligned16(d_out) || !aligned16(d_ws)) return HE_EINVAL;
-    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    uint32_t *xn = (uint32_t *)d_ws;
-    uint32_t *mac = (uint32_t *)((char *)d_ws + x_bytes(ly, B));
-    const hipError_t e = inputs_ntt(ctx, ly, B, d_c0, d_sh, xn, st);
-    if (e != hipSuccess) return dev_fail(e, "conv forward ntt");
-    return conv_from_x(ctx, ly, B, xn, d_sh != nullptr, d_sh_next, d_out, mac, st);
+    return he_layer_call_sync(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, d_ws, ws_bytes,
+                              ctx_sync(ctx, (hipStream_t)stream), stream);
 }
 
 int he_conv_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
@@ -1264,10 +1435,11 @@ int he_conv_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d
     if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_CONV) return HE_EINVAL;
     if (B == 0) return HE_OK;
     void *ws = nullptr;
+    uint32_t *sync = nullptr;
     const size_t need = layer_ws_bytes(ly, B);
-    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws, &sync);
     if (rc != HE_OK) return rc;
-    return he_conv_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, stream);
+    return he_layer_call_sync(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, sync, stream);
 }
 
 int he_conv_layer_noalloc(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
@@ -1289,8 +1461,9 @@ int he_conv_layer_noalloc(he_ctx *ctx, const he_layer *ly, uint32_t B, const uin
     // timing events are created per launch when profiling is on; this form creates none
     const bool saved = tl_no_prof;
     tl_no_prof = true;
-    const int rc = he_conv_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, (size_t)HE_NOALLOC_SCRATCH_BYTES,
-                                    stream);
+    uint32_t *sync = (uint32_t *)((char *)ws + HE_NOALLOC_SCRATCH_BYTES);
+    const int rc = he_layer_call_sync(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, (size_t)HE_NOALLOC_SCRATCH_BYTES,
+                                      sync, stream);
     tl_no_prof = saved;
     return rc;
 }
@@ -1298,16 +1471,8 @@ int he_conv_layer_noalloc(he_ctx *ctx, const he_layer *ly, uint32_t B, const uin
 int he_fc_layer_ws(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
                    const uint32_t *d_sh_next, uint32_t *d_out, void *d_ws, size_t ws_bytes, void *stream) {
     if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_FC) return HE_EINVAL;
-    if (B == 0) return HE_OK;
-    if (!d_c0 || !d_out || !d_ws) return HE_EINVAL;
-    if (!aligned16(d_c0) || !aligned16(d_ws)) return HE_EINVAL;
-    if (ws_bytes < layer_ws_bytes(ly, B)) return HE_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    uint32_t *xn = (uint32_t *)d_ws;
-    uint32_t *mac = (uint32_t *)((char *)d_ws + x_bytes(ly, B));
-    const hipError_t e = inputs_ntt(ctx, ly, B, d_c0, d_sh, xn, st);
-    if (e != hipSuccess) return dev_fail(e, "fc forward ntt");
-    return fc_from_x(ctx, ly, B, xn, d_sh != nullptr, d_sh_next, d_out, mac, st);
+    return he_layer_call_sync(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, d_ws, ws_bytes,
+                              ctx_sync(ctx, (hipStream_t)stream), stream);
 }
 
 int he_fc_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
@@ -1315,10 +1480,11 @@ int he_fc_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c
     if (!ctx || !ly || ly->ctx != ctx || ly->info.kind != HE_LAYER_FC) return HE_EINVAL;
     if (B == 0) return HE_OK;
     void *ws = nullptr;
+    uint32_t *sync = nullptr;
     const size_t need = layer_ws_bytes(ly, B);
-    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws, &sync);
     if (rc != HE_OK) return rc;
-    return he_fc_layer_ws(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, stream);
+    return he_layer_call_sync(ctx, ly, B, d_c0, d_sh, d_sh_next, d_out, ws, need, sync, stream);
 }
 
 int he_layer_inputs_ntt(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0, const uint32_t *d_sh,
@@ -1336,10 +1502,12 @@ int he_conv_layer_ntt(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_
     if (B == 0) return HE_OK;
     if (!d_x || !d_out || !aligned16(d_x) || !aligned16(d_out)) return HE_EINVAL;
     void *ws = nullptr;
+    uint32_t *sync = nullptr;
     const size_t need = layer_ws_bytes(ly, B) - x_bytes(ly, B);
-    int rc = ctx_workspace(ctx, (hipStream_t)stream, need > 0 ? need : 256, &ws);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need > 0 ? need : 256, &ws, &sync);
     if (rc != HE_OK) return rc;
-    return conv_from_x(ctx, ly, B, d_x, has_sh != 0, d_sh_next, d_out, (uint32_t *)ws, (hipStream_t)stream);
+    return layer_exec(ctx, ly, B, nullptr, nullptr, d_x, has_sh != 0, d_sh_next, d_out, ws, sync,
+                      (hipStream_t)stream);
 }
 
 int he_fc_layer_ntt(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_x, int has_sh,
@@ -1348,10 +1516,12 @@ int he_fc_layer_ntt(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t 
     if (B == 0) return HE_OK;
     if (!d_x || !d_out || !aligned16(d_x)) return HE_EINVAL;
     void *ws = nullptr;
+    uint32_t *sync = nullptr;
     const size_t need = layer_ws_bytes(ly, B) - x_bytes(ly, B);
-    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws);
+    int rc = ctx_workspace(ctx, (hipStream_t)stream, need, &ws, &sync);
     if (rc != HE_OK) return rc;
-    return fc_from_x(ctx, ly, B, d_x, has_sh != 0, d_sh_next, d_out, (uint32_t *)ws, (hipStream_t)stream);
+    return layer_exec(ctx, ly, B, nullptr, nullptr, d_x, has_sh != 0, d_sh_next, d_out, ws, sync,
+                      (hipStream_t)stream);
 }
 
 int he_ntt_forward(he_ctx *ctx, uint32_t rows, const uint32_t *d_in, uint32_t *d_out, void *stream) {

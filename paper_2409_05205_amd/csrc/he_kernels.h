@@ -128,6 +128,40 @@ hipError_t launch_mac_tail(const uint32_t *X, const uint32_t *Op, uint32_t *out,
                            uint32_t N, uint32_t s, const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
                            hipStream_t st, const LaunchEv *ev = nullptr);
 
+// One launch per layer call (kernels_fused.hip): forward NTT of the input rows, coefficient-wise
+// MAC and inverse with extraction, as work items in workgroup order that wait on counters in a
+// zeroed sync block of FZ_SYNC_WORDS words (left zero again when the launch ends).
+enum { FZ_KIND_CONV = 0, FZ_KIND_FC = 1 };
+enum { FZ_SB_ERR = 2, FZ_SB_HDR = 64, FZ_SYNC_WORDS = 16384 };
+struct FusedLayer {
+    const uint32_t *c0;       // [B][K_in][L][N] coefficient form (ntt_c0 = K_in), else unused
+    const uint32_t *sh;       // [B][K_in][N] shares (ntt_sh = K_in), else unused
+    const uint32_t *sh_next;  // conv [B][K_out][N]; fc [B][blocks][n_o_p]; or null
+    uint32_t *out;            // conv [B][K_out][L][N]; fc [B][blocks][L][n_o_p]
+    const uint32_t *op;       // resident operands [rows][L][Jtot][N]
+    const int32_t *bias;      // fc [blocks][n_o_p]
+    uint32_t *x;              // NTT-domain inputs [B][Jtot][L][N] (written by the NTT items)
+    uint32_t *h;              // conv block sums [B][c_o][L][N/s]; fc chunk shares [B][blocks][L][N/1024][n_o_p]
+    uint32_t kind;            // FZ_KIND_CONV (residue-class form) or FZ_KIND_FC
+    uint32_t B, K_in, Jtot, Juse;
+    uint32_t rows;            // c_o (conv) or blocks (fc)
+    uint32_t g_o, K_out, L, logN, s_log, n_o_p;
+    uint32_t ntt_c0, ntt_sh;  // input rows per image transformed in this launch (K_in or 0 each)
+    uint32_t rows_form;       // conv: 1 = whole-row NTT items and one MAC + tail item per output row
+                              // (1024-thread workgroups); 0 = sub-block NTT, MAC chunk and tail items
+    // filled by fused_layer_plan
+    uint32_t ng, mac_per_bl, tail_rw, n_ntt, n_mac, n_inv, n_ctr, ctr_stride;
+};
+// Whether the one-launch form handles this layer shape (N 4096..16384; conv 2 <= s <= 256 with
+// N/s <= 4096; fc n_o' <= 1024).
+bool fused_layer_ok(const FusedLayer &jb);
+// Item counts, per-item geometry and counter spacing; returns the words the launch's counters
+// span past FZ_SB_HDR.
+uint32_t fused_layer_plan(FusedLayer &jb);
+hipError_t launch_fused_layer(const FusedLayer &jb, const uint32_t *tw, const uint32_t *twsh, const uint32_t *twi,
+                              const uint32_t *twish, const uint32_t *xinv, const LimbConsts &lc, uint32_t *sync,
+                              hipStream_t st, const LaunchEv *ev = nullptr);
+
 // Client masks from the server's resident operands (kernels_client.hip): noise rows into the
 // operand layout, then the combination with NTT(b) (in place on E).
 hipError_t launch_mask_noise(const int32_t *e1, const int32_t *e2, uint32_t *E, uint32_t K_in, uint32_t n_rows,

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/he.h"
+#include "he_internal.h"
 #include "he_kernels.h"
 
 namespace {
@@ -32,6 +33,7 @@ struct he_seq {
     std::vector<Step> steps;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    uint32_t *sync = nullptr;   // counter block of the one-launch layer form (steps run in stream order)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -51,9 +53,7 @@ int grow(he_seq *s, size_t need) {
 
 int run_steps(he_seq *s, hipStream_t st) {
     for (const Step &p : s->steps) {
-        int rc = (p.kind == HE_LAYER_CONV)
-                     ? he_conv_layer_ws(s->ctx, p.ly, p.B, p.c0, p.sh, p.shn, p.out, s->ws, s->ws_bytes, st)
-                     : he_fc_layer_ws(s->ctx, p.ly, p.B, p.c0, p.sh, p.shn, p.out, s->ws, s->ws_bytes, st);
+        const int rc = he_layer_call_sync(s->ctx, p.ly, p.B, p.c0, p.sh, p.shn, p.out, s->ws, s->ws_bytes, s->sync, st);
         if (rc != HE_OK) return rc;
     }
     return HE_OK;
@@ -68,6 +68,11 @@ int he_seq_create(he_ctx *ctx, he_seq **out) {
     he_seq *s = new (std::nothrow) he_seq();
     if (!s) return HE_ENOMEM;
     s->ctx = ctx;
+    s->sync = he_sync_block_alloc();
+    if (!s->sync) {
+        delete s;
+        return HE_ENOMEM;
+    }
     *out = s;
     return HE_OK;
 }
@@ -128,6 +133,7 @@ void he_seq_free(he_seq *s) {
     if (s->exec) hipGraphExecDestroy(s->exec);
     if (s->graph) hipGraphDestroy(s->graph);
     if (s->ws) hipFree(s->ws);
+    if (s->sync) hipFree(s->sync);
     delete s;
 }
 

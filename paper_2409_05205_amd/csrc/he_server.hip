@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "../../include/he.h"
+#include "he_internal.h"
 
 namespace {
 
@@ -58,6 +59,7 @@ struct Req {
 struct Slot {
     hipStream_t st = nullptr;
     hipEvent_t done = nullptr;
+    uint32_t *sync = nullptr;           // counter block of the one-launch layer form on this stream
     bool busy = false;
     std::vector<uint32_t> reqs;
     size_t off = 0, bytes = 0;          // pool allocation
@@ -147,8 +149,7 @@ int launch_batch(he_server *s, Slot &sl, const std::vector<uint32_t> &ids) {
     const bool has_sh = h.sh != nullptr, has_shn = h.shn != nullptr;
     int rc;
     if (B == 1) {
-        rc = conv ? he_conv_layer_ws(L.ctx, L.ly, 1, h.c0, h.sh, h.shn, h.out, ws, ws_bytes, sl.st)
-                  : he_fc_layer_ws(L.ctx, L.ly, 1, h.c0, h.sh, h.shn, h.out, ws, ws_bytes, sl.st);
+        rc = he_layer_call_sync(L.ctx, L.ly, 1, h.c0, h.sh, h.shn, h.out, ws, ws_bytes, sl.sync, sl.st);
     } else {
         uint32_t *c0 = (uint32_t *)(base + ws_bytes);
         uint32_t *sh = (uint32_t *)((char *)c0 + a256(B * L.c0_words * 4));
@@ -166,10 +167,8 @@ int launch_batch(he_server *s, Slot &sl, const std::vector<uint32_t> &ids) {
                                           sl.st) != hipSuccess)
                 return HE_EDEVICE;
         }
-        rc = conv ? he_conv_layer_ws(L.ctx, L.ly, B, c0, has_sh ? sh : nullptr, has_shn ? shn : nullptr, out, ws,
-                                     ws_bytes, sl.st)
-                  : he_fc_layer_ws(L.ctx, L.ly, B, c0, has_sh ? sh : nullptr, has_shn ? shn : nullptr, out, ws,
-                                   ws_bytes, sl.st);
+        rc = he_layer_call_sync(L.ctx, L.ly, B, c0, has_sh ? sh : nullptr, has_shn ? shn : nullptr, out, ws,
+                                ws_bytes, sl.sync, sl.st);
         if (rc == HE_OK) {
             for (uint32_t i = 0; i < B; ++i) {
                 const Req &r = s->reqs[ids[i]];
@@ -342,7 +341,7 @@ int he_server_create(const he_server_config *cfg, he_server **out) {
     s->slots.resize(cfg->streams);
     for (Slot &sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess || !(sl.sync = he_sync_block_alloc())) {
             he_server_free(s);
             return HE_EDEVICE;
         }
@@ -458,6 +457,7 @@ void he_server_free(he_server *s) {
         if (sl.st) hipStreamSynchronize(sl.st);
         if (sl.done) hipEventDestroy(sl.done);
         if (sl.st) hipStreamDestroy(sl.st);
+        if (sl.sync) hipFree(sl.sync);
     }
     if (s->pool_base) hipFree(s->pool_base);
     delete s;

@@ -35,10 +35,11 @@ EXPORTED = [
     "he_layer_inputs_ntt", "he_conv_layer_ntt", "he_fc_layer_ntt",
     "he_pack_operands", "he_client_masks", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
     "he_layer_geometry", "he_ctx_workspace_bytes", "he_workspace_reserve", "he_conv_layer_noalloc",
+    "he_sync_check",
 ]
 NOALLOC_SCRATCH_BYTES = 32 << 20   # HE_NOALLOC_SCRATCH_BYTES in include/he.h
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
-HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL = 1, 2, 4, 8, 16
+HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL, HE_K_LAYER = 1, 2, 4, 8, 16, 32
 
 
 class HEError(RuntimeError):
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("he_conv_layer", "he_fc_layer"):
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
     lib.he_conv_layer_noalloc.argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
+    lib.he_sync_check.argtypes = [VP, VP]
     for name in ("he_conv_layer_ws", "he_fc_layer_ws"):
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP, SZ, VP]
     lib.he_layer_inputs_ntt.argtypes = [VP, VP, U32, VP, VP, VP, VP]
@@ -260,6 +262,10 @@ class Context:
             return
         _check(load_library().he_workspace_reserve(self.handle, h, nbytes), "he_workspace_reserve")
         self._reserved[h] = nbytes
+
+    def sync_check(self, stream=None) -> None:
+        """Raise if a one-launch layer call on `stream` gave up a wait (he_sync_check)."""
+        _check(load_library().he_sync_check(self.handle, _stream(stream)), "he_sync_check")
 
     def geometry(self, spec, flags: int = HE_PACK_CLASS_INTT) -> "LayerInfo":
         """The library's tiling of a layer description, before packing (he_layer_geometry)."""
