@@ -457,50 +457,74 @@ def resnet50_form(he, args, stream, sync):
 
 
 # ------------------------------------------------------------------ CPU baseline
-def cpu_baseline(reps=3):
-    """The oracle's server evaluation of the x1 stack on host cores, one image: every distinct layer
-    shape timed `reps` times (mean) and weighted by its count in the 20-layer stack (the layers of
-    one shape differ only in their values)."""
-    from oracle import bfv, packing
-    N = 8192
-    ctx = bfv.make_ctx(N, 4, wl.T_PLAIN)
+def _host_description():
+    """nproc and the CPU model of this host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
+def cpu_baseline(reps_one=1, reps_all=3):
+    """The oracle's plain C build (textbook NTT, u64 % reduction, -O2, OpenMP over (limb, channel)
+    units) over every layer of the x1 stack for one image, on one core and on all host cores.  The
+    set-up transforms of the masks and filters (kept by the server, Sec. IV-A-1) are not timed."""
+    from oracle import bfv, cserver, packing
+    N, L = 8192, 4
+    ctx = bfv.make_ctx(N, L, wl.T_PLAIN)
     layers = wl.plain20(1, 10)
     cfg = wl.CONFIG_PLAIN20_X1
-    counts = {}
+    calls = []
     for k, shp in enumerate(layers):
-        counts.setdefault(shp, []).append(k)
-    t_stack = t_sample = 0.0
-    for shp, ks in counts.items():
-        k = ks[0]
         if shp.kind == "conv":
             g = packing.conv_geometry(N, shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
             F = wl.layer_weights(cfg, 1, k, shp)
             rho = wl.mask_polys(cfg, 1, k, g.K_in * shp.c_o, N).reshape(g.K_in, shp.c_o, N)
+            ops = cserver.conv_setup(ctx, rho, packing.pack_conv_filters(F, g), 0)
             c0 = wl.ciphertext_polys(cfg, 0, 1, k, g.K_in, ctx.primes, N).astype(np.uint64)
             sh = None if k == 0 else wl.share_polys(cfg, 0, 1, k, g.K_in, N)
             shn = wl.share_polys(cfg, 0, 1, k, g.K_out, N, "shnext")
-            fh = packing.pack_conv_filters(F, g)
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                bfv.server_conv(ctx, g, c0, rho, fh, sh, shn)
+            calls.append(lambda th, g=g, c0=c0, ops=ops, sh=sh, shn=shn:
+                         cserver.server_conv(ctx, g, c0, ops, sh, shn, th))
         else:
             g = packing.fc_geometry(N, shp.n_i, shp.n_o)
             w = packing.pack_fc_weights(wl.layer_weights(cfg, 1, k, shp), g)
             d = packing.pack_fc_bias(wl.layer_bias(cfg, 1, k, shp), g)
-            rho = wl.mask_polys(cfg, 1, k, g.blocks, N)
+            ops = cserver.fc_setup(ctx, wl.mask_polys(cfg, 1, k, g.blocks, N), w, 0)
             c0 = wl.ciphertext_polys(cfg, 0, 1, k, 1, ctx.primes, N)[0].astype(np.uint64)
             sh = wl.share_polys(cfg, 0, 1, k, 1, N)[0]
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                bfv.server_fc(ctx, g, c0, rho, w, d, sh, None)
-        dt = time.perf_counter() - t0
-        t_sample += dt
-        t_stack += dt / reps * len(ks)
-    return {"value": len(layers) / t_stack, "unit": "layers/s", "cores": 1, "kind": "oracle",
-            "sample": f"numpy oracle server evaluation, one image: each of the {len(counts)} distinct layer "
-                      f"shapes of the x1 stack (N=8192, 4 limbs) {reps} times, {t_sample:.1f} s single-threaded; "
-                      f"the mean per shape weighted by shape counts gives {t_stack:.1f} s for the "
-                      f"{len(layers)}-layer stack"}
+            calls.append(lambda th, g=g, c0=c0, ops=ops, d=d, sh=sh: cserver.server_fc(ctx, g, c0, ops, d, sh, None, th))
+
+    def stack_s(threads, reps):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for fn in calls:
+                fn(threads)
+        return (time.perf_counter() - t0) / reps
+
+    nproc, model = _host_description()
+    # the host cores this process may use (OMP_NUM_THREADS, where set, caps them)
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (nproc or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        avail = min(avail, int(os.environ["OMP_NUM_THREADS"]))
+    t_one = stack_s(1, reps_one)
+    threads = cserver.threads_used(avail)
+    t_all = stack_s(threads, reps_all)
+    n = len(layers)
+    return {"value": round(n / t_all, 2), "unit": "layers/s", "cores": threads, "kind": "oracle",
+            "sample": f"plain C build of the oracle's server evaluation (oracle/c/he_oracle.c: textbook NTT, u64 "
+                      f"% reduction, gcc -O2, OpenMP over (limb, channel) units): the whole {n}-layer x1 stack "
+                      f"(N=8192, 4 limbs), one image, {reps_all} passes on {threads} threads; set-up transforms of "
+                      f"the masks and filters untimed",
+            "single_core": {"value": round(n / t_one, 2), "unit": "layers/s", "cores": 1,
+                            "s_per_image": round(t_one, 3), "passes": reps_one},
+            "s_per_image": round(t_all, 3), "nproc": nproc, "cpu_model": model}
 
 
 # ------------------------------------------------------------------ main

@@ -17,6 +17,9 @@ Modules
   network  integer conv / FC reference, plain-20 harness between layers
   counts   Table I / Table III operation counts (and the generalised packing's
            per-layer counts that reduce to them) and Table II byte formulas
+  cserver  ctypes binding of c/he_oracle.c, a plain C build of the server
+           evaluation (same steps as bfv.server_conv / server_fc, timed as the
+           CPU baseline; checked against bfv and the stored digests)
 
 Parity notes: every function is pinned by a CPU test against a closed form,
 a brute-force definition, an invariant or a value printed in the paper, except
