@@ -384,6 +384,69 @@ def paper_protocol_form(he, ctx, st, stream, steps, warmup, sync):
         return time_loop(g.replay, steps, warmup, sync)
 
 
+def single_conv_form(he, args, stream, sync):
+    """The single conv workload (conv 3->16 on 3x32x32, pad 1, N = 4096, 3 limbs, a network's first
+    layer: no input share, a fresh output share): layer calls back to back (throughput), per-call
+    latency with a synchronisation after each call (p50 / p99), and the kernel time per launch kind
+    against HBM (algorithmic bytes of the launches that carry the layer)."""
+    import torch
+    N, L = 4096, 3
+    ctx = he.Context(N, L, wl.T_PLAIN)
+    shp = wl.single_conv_layer()
+    spec = he.ConvSpec(shp.c_i, shp.c_o, shp.H, shp.W, shp.f, shp.stride, shp.pad)
+    til = ctx.geometry(spec)
+    cfg = wl.CONFIG_SINGLE_CONV
+    W = wl.layer_weights(cfg, 0, 0, shp)
+    rho = wl.mask_polys(cfg, 0, 0, til.K_in * shp.c_o, N).reshape(til.K_in, shp.c_o, N)
+    ly = ctx.pack_conv(spec, W, rho)
+    dev = torch.device("cuda:0")
+    c0 = torch.from_numpy(wl.ciphertext_polys(cfg, 0, 0, 0, til.K_in, ctx.primes, N)
+                          .reshape(1, til.K_in, L, N).astype(np.int32)).to(dev)
+    shn = torch.from_numpy(wl.share_polys(cfg, 0, 0, 0, til.K_out, N, "shnext").reshape(1, til.K_out, N)
+                           .astype(np.int32)).to(dev)
+    if not args.no_tune:
+        ctx.autotune(ly, 1)
+    seq = he.Sequence(ctx)
+    seq.add(ly, c0, None, shn)
+    reps = max(200, args.steps)
+    with torch.cuda.stream(stream):
+        T = time_loop(lambda: seq.run(stream), reps, 20, sync)
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ctx.conv_layer(ly, c0, None, shn, stream=stream)
+        stream.synchronize()
+        lat.append(time.perf_counter() - t0)
+    kinds = [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL), ("intt", he.HE_K_INTT),
+             ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER)]
+    ctx.profile_reset()
+    ctx.profile_enable(sum(k for _, k in kinds))
+    with torch.cuda.stream(stream):
+        time_loop(lambda: seq.run(stream), 100, 0, sync)
+    kern = {}
+    for name, kind in kinds:
+        n, ms = ctx.profile_read(kind)
+        if n:
+            kern[name] = {"launches_per_call": n // 100, "avg_us": round(ms * 1e3 / n, 3)}
+    ctx.profile_enable(0)
+    ctx.profile_reset()
+    # algorithmic bytes of the call: c0 read, resident operand rows (c0 rows only: no input share)
+    # read once, sh' read, output polynomials written
+    nbytes = (til.K_in * L * N + til.K_in * shp.c_o * L * N + til.K_out * N + til.K_out * L * N) * 4
+    call_us = sum(v["avg_us"] * v["launches_per_call"] for v in kern.values())
+    ach = nbytes / (call_us * 1e-6) / 1e9
+    out = {"workload": "conv 3->16 on 3x32x32, pad 1, N=4096, 3 limbs, first layer (no input share)",
+           "layers_per_s": round(reps / T, 1), "ms_per_layer": round(T / reps * 1e3, 4),
+           "latency_p50_ms": round(percentile(lat, 50) * 1e3, 4),
+           "latency_p99_ms": round(percentile(lat, 99) * 1e3, 4), "kernels": kern,
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_call": nbytes,
+                        "kernel_us_per_call": round(call_us, 3)}}
+    log(f"single_conv: {json.dumps(out)}")
+    ly.free()
+    return out
+
+
 def resnet50_form(he, args, stream, sync):
     """ResNet-50-shaped layers (the body after the stem: 52 convs + FC 2048 -> 1000) at
     N = 16384, 6 limbs.  Each distinct shape is packed, tuned and timed on its own (resident
@@ -542,9 +605,13 @@ def main():
     ap.add_argument("--batched-mac", type=int, default=None,
                     help="pin the MAC variant of the batched form (HE_TUNE_MAC value) instead of tuning it")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=6000)
-    ap.add_argument("--served-warmup", type=int, default=500)
+    ap.add_argument("--served-requests", type=int, default=20000)
+    ap.add_argument("--served-warmup", type=int, default=1000)
     ap.add_argument("--served-rate", type=float, default=2000.0)
+    ap.add_argument("--served-sweep", default="2000,8000,16000,32000,64000",
+                    help="offered rates (req/s) of the load sweep, served against plain FCFS at each ('' skips)")
+    ap.add_argument("--sweep-requests", type=int, default=4000)
+    ap.add_argument("--no-single", action="store_true", help="skip the single conv workload (N=4096, 3 limbs)")
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--stress-clients", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
@@ -736,6 +803,10 @@ def main():
     }
     del seq_g
 
+    # ---------------- single conv workload: conv 3->16 on 3x32x32, N = 4096, 3 limbs, one image
+    if not args.no_single:
+        result["forms"]["single_conv"] = single_conv_form(he, args, stream, sync)
+
     # ---------------- batched: 64 images x widths 1, 2, 4
     if not args.no_batched:
         bres = {}
@@ -792,7 +863,8 @@ def main():
         for name, streams, mb in [("served", 4, 8), ("plain_fcfs", 1, 1)]:
             res = serve.run_trace(variants, buffers, arrival, ltype, client, streams, mb, budget, timeout_s=300)
             st = serve.latency_stats(res, args.served_warmup)
-            st.update({"streams": streams, "max_batch": mb, "rc": res["rc"]})
+            st.update({"streams": streams, "max_batch": mb, "rc": res["rc"],
+                       "valid": res["rc"] == 0 and st["failed"] == 0})
             sres[name] = st
             log(f"{name}: {json.dumps(st)}")
         # capacity: the whole trace arrives at once
@@ -805,6 +877,22 @@ def main():
             sres[name] = {"requests": sat_n, "layers_per_s": sat_n / span, "mean_batch": float(res["batch"].mean()),
                           "rc": res["rc"]}
             log(f"{name}: {json.dumps(sres[name])}")
+        # offered-load sweep: served against plain FCFS on the same trace at each rate
+        sweep = []
+        for rate in [float(r) for r in args.served_sweep.split(",") if r.strip()]:
+            m = args.sweep_requests
+            w = m // 10
+            arr, lt, cl = serve.poisson_trace(rate, m + w, n_types, clients, seed=2)
+            row = {"offered_req_per_s": rate, "requests": m, "warmup_requests": w}
+            for name, streams, mb in [("served", 4, 8), ("plain_fcfs", 1, 1)]:
+                res = serve.run_trace(variants, buffers, arr, lt, cl, streams, mb, budget, timeout_s=300)
+                st = serve.latency_stats(res, w)
+                st["rc"] = res["rc"]
+                st["valid"] = res["rc"] == 0 and st["failed"] == 0
+                row[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+            log(f"sweep {json.dumps(row)}")
+            sweep.append(row)
+        sres["sweep"] = sweep
         result["forms"]["served"] = sres
         del variants, buffers
         torch.cuda.empty_cache()

@@ -12,8 +12,10 @@ server-kernel call per layer gives it for all clients at once (the last layer
 uses an FC layer packed without bias).  The extra r_t f-hat term this adds is
 far below Delta.  The integer reference runs on the device in float64 (exact
 for these magnitudes) and is checked against the oracle's forward pass for two
-clients; client 0's first and last layers are also compared word for word
-with the oracle's own encryption and server evaluation.
+clients.  For the first 8 clients, the first, a middle and the last layer are
+also compared word for word with the oracle: the oracle's own encryption of the
+same plaintext (numpy), and its server evaluation of those ciphertexts (the C
+build, which the CPU suite pins to the numpy oracle and the stored digests).
 """
 import os
 
@@ -21,7 +23,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from oracle import bfv, network, packing
+from oracle import bfv, cserver, network, packing
 from gpu_helpers import host
 
 pytestmark = pytest.mark.gpu
@@ -30,6 +32,8 @@ T = wl.T_PLAIN
 CLIENTS = int(os.environ.get("HE_STRESS_CLIENTS", "256"))
 CFG = wl.CONFIG_STRESS
 WIDTH = 4
+ORACLE_CLIENTS = 8
+ORACLE_LAYERS = (0, 9, 19)      # first conv, a stage-two conv (128 -> 128 at 16 x 16), the FC head
 
 
 def _forward_gpu(imgs, shapes, Ws, Bs):
@@ -163,15 +167,17 @@ def test_stress_x4_clients_decrypt_exact():
             bufs.append(serve.LayerBuffers(c0[:, 0].contiguous(), sh[:, 0].to(torch.int32).contiguous(), None,
                                            torch.empty(outshape, dtype=torch.int32, device="cuda:0")))
         side.append(dict(c0p=c0p, shp=shp_, sh=sh, shn=shn))
-        if k in (0, len(shapes) - 1):
-            # client 0: the oracle's own encryption and server evaluation, word for word
-            s0, a0, e_0, b0 = keys[0]
-            ob = bfv.keygen(octx, s0, a0, e_0)
-            assert (host(b0[None])[0] == ob).all()
-            oc0 = np.stack([bfv.encrypt_c0(octx, i_poly[0, j].cpu().numpy(), vv[0, j].cpu().numpy(),
-                                           e0[0, j].cpu().numpy(), ob) for j in range(K_in)])
-            assert (host(c0[0:1])[0] == oc0).all(), f"encryption layer {k}"
-            side[-1]["oc0"] = oc0
+        if k in ORACLE_LAYERS:
+            # the first clients: the oracle's own encryption, word for word
+            side[-1]["oc0"] = []
+            for c in range(min(C, ORACLE_CLIENTS)):
+                s0, a0, e_0, b0 = keys[c]
+                ob = bfv.keygen(octx, s0, a0, e_0)
+                assert (host(b0[None])[0] == ob).all(), f"key of client {c}"
+                oc0 = np.stack([bfv.encrypt_c0(octx, i_poly[c, j].cpu().numpy(), vv[c, j].cpu().numpy(),
+                                               e0[c, j].cpu().numpy(), ob) for j in range(K_in)])
+                assert (host(c0[c:c + 1])[0] == oc0).all(), f"encryption layer {k} client {c}"
+                side[-1]["oc0"].append(oc0)
         print(f"encrypted layer {k}", flush=True)
 
     res = serve.run_clients(v, bufs, C, streams=4, max_batch=16, budget=24 << 30, timeout_s=600)
@@ -194,19 +200,24 @@ def test_stress_x4_clients_decrypt_exact():
             dec = msg[:, torch.as_tensor(p, device="cuda:0"), torch.as_tensor(kk, device="cuda:0")]
             dec = torch.where(dec > T // 2, dec - T, dec).reshape(C, g.c_o, g.H_o, g.W_o)
             assert torch.equal(dec, outs[k]), f"layer {k}: decrypted output differs from the integer conv"
-            if k == 0:
-                rho0 = wl.mask_polys(CFG, WIDTH, 0, g.K_in * g.c_o, N).reshape(g.K_in, g.c_o, N)
-                want = bfv.server_conv(octx, g, side[k]["oc0"], rho0, packing.pack_conv_filters(Ws[0], g), None,
-                                       shn[0].cpu().numpy())
-                assert (host(out[0:1])[0] == want).all(), "server words of client 0, layer 0"
+            if k in ORACLE_LAYERS:
+                rho = wl.mask_polys(CFG, WIDTH, k, g.K_in * g.c_o, N).reshape(g.K_in, g.c_o, N)
+                ops = cserver.conv_setup(octx, rho, packing.pack_conv_filters(Ws[k], g), 0)
+                for c, oc0 in enumerate(side[k]["oc0"]):
+                    sh_c = None if side[k]["sh"] is None else side[k]["sh"][c].cpu().numpy()
+                    shn_c = None if shn is None else shn[c].cpu().numpy()
+                    want = cserver.server_conv(octx, g, oc0, ops, sh_c, shn_c, 0)
+                    assert (host(out[c:c + 1])[0] == want).all(), f"server words of client {c}, layer {k}"
         else:
             c1 = ctx.fc_layer(fc_nobias, c0p[:, 0].contiguous(), shp_[:, 0].contiguous(), None)
             msg = ctx.decrypt(out.reshape(C * fg.blocks, L, fg.n_o_p), c1.reshape(C * fg.blocks, L, fg.n_o_p)).long()
             msg = msg.reshape(C, fg.blocks * fg.n_o_p)[:, :fg.n_o]
             dec = torch.where(msg > T // 2, msg - T, msg)
             assert torch.equal(dec, outs[k]), "FC: decrypted output differs from the integer FC"
-            want = bfv.server_fc(octx, fg, side[k]["oc0"][0], wl.mask_polys(CFG, WIDTH, 19, fg.blocks, N),
-                                 packing.pack_fc_weights(Ws[-1], fg), packing.pack_fc_bias(Bs[-1], fg),
-                                 side[k]["sh"][0, 0].cpu().numpy(), None)
-            assert (host(out[0:1])[0] == want).all(), "server words of client 0, FC"
+            ops = cserver.fc_setup(octx, wl.mask_polys(CFG, WIDTH, 19, fg.blocks, N),
+                                   packing.pack_fc_weights(Ws[-1], fg), 0)
+            for c, oc0 in enumerate(side[k]["oc0"]):
+                want = cserver.server_fc(octx, fg, oc0[0], ops, packing.pack_fc_bias(Bs[-1], fg),
+                                         side[k]["sh"][c, 0].cpu().numpy(), None, 0)
+                assert (host(out[c:c + 1])[0] == want).all(), f"server words of client {c}, FC"
         print(f"checked layer {k}", flush=True)
