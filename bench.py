@@ -34,68 +34,100 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Shoup Cooley-Tukey butterflies per second of the whole chip (256 CUs, 2.4 GHz): 7.3 per CU-clock,
-# measured at full occupancy for this instruction mix (mul_hi + 2 mul_lo + 6 add/compare).
+CUS, CLOCK_GHZ = 256, 2.4
+# Integer-ALU roofs (whole chip, G operations per second): measured by he_probe_rate
+# (csrc/kernels_probe.hip) and replaced by the run's own measurement when --rates is on (the
+# default).  A Shoup butterfly is 9 vector instructions (1 mul_hi, 2 mul_lo, 6 add / sub / min);
+# the MAC's inner product is one v_mad_u64_u32 per product.
 BFLY_PEAK_G = 4470.0
-# 32x32->64-bit multiply-adds (v_mad_u64_u32) per second of the whole chip, measured the same way:
-# the issue-rate ceiling of the MAC's inner product.
+GSBFLY_PEAK_G = 4470.0
 MAD64_PEAK_G = 22400.0
+
+
+def alu_rates(he):
+    """Measured integer-ALU rates of the chip (he_probe_rate), as G ops/s and per CU-clock."""
+    out = {}
+    for name, kind in [("butterfly_ct", he.HE_PROBE_BFLY), ("butterfly_gs", he.HE_PROBE_GSBFLY),
+                       ("mad_u64_u32", he.HE_PROBE_MAD64), ("add_u32", he.HE_PROBE_ADD),
+                       ("mul_lo_u32", he.HE_PROBE_MULLO), ("mul_hi_u32", he.HE_PROBE_MULHI)]:
+        ops, ms = he.probe_rate(kind, 8192)
+        out[name] = {"G_per_s": round(ops / 1e9, 1), "per_CU_clock": round(ops / (CUS * CLOCK_GHZ * 1e9), 3),
+                     "ms": round(ms, 3)}
+    return out
 # HBM traffic per launch from the FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a 256 MiB
-# copy), valid while the kernel source is the one that was measured.
+# copy: FETCH_SIZE x 2, WRITE_SIZE x 1), valid while the kernel source is the one that was measured.
 PMC_TRAFFIC = {
-    # launches carrying the MAC in the plain form: k_mac_tail (fused) and k_mac_class / k_mac_full
-    # (split), measured per layer of the stack with every layer pinned to each form in turn; the
-    # traffic of a run is the mean over its layers of the entry of the form each layer ran in
-    "mac": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/kernels_mac.hip'],
-            "sha256": "ddf2fb4e3b70cdccf81ed56c02e2b36f8ba2c1dda9e26dc75cc0839a4b6718bf",
-            "per_layer": [
-                {"F": 4729906, "S": 2793775},
-                {"F": 21240682, "S": 18389255},
-                {"F": 21241011, "S": 18389109},
-                {"F": 21240718, "S": 18388963},
-                {"F": 21240645, "S": 18388963},
-                {"F": 21240627, "S": 18388817},
-                {"F": 21240682, "S": 18389109},
-                {"F": 40113302, "S": 35688525},
-                {"F": 19041807, "S": 17602742},
-                {"F": 19041697, "S": 17602596},
-                {"F": 19041789, "S": 17602596},
-                {"F": 19041515, "S": 17602742},
-                {"F": 19041716, "S": 17602596},
-                {"F": 36865530, "S": 34640929},
-                {"F": 17951146, "S": 17209413},
-                {"F": 17951219, "S": 17209559},
-                {"F": 17951457, "S": 17209413},
-                {"F": 17951164, "S": 17209413},
-                {"F": 17951384, "S": 17209449},
-                {"F": None, "S": 704441}
-            ]},
-    "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip'],
-                "sha256": "d4d5ba2710f6548c279d3d4e646dc285a3f5d523711e5410236c1966cb51d561",
-                "bytes_per_launch": 2833897},
+    # the launch that carries each layer's MAC, per layer of the stack with every layer pinned to each
+    # form in turn: k_mac_tail (F, fused MAC and inverse), k_mac_class / k_mac_full (S, split), and
+    # the whole layer in one launch, k_fused_layer (O) or k_fused_rows (R; the FC head runs O).  Each
+    # form is valid while the sources of its kernels are the ones that were measured.
+    "layers": {
+        "forms": {
+            "F": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
+                  "sha256": "619acfff01cfa3e3e18ee784bf8138d685ebe74da9abf6577da2bcae7f1f0906"},
+            "S": {"sources": ['paper_2409_05205_amd/csrc/kernels_mac.hip', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
+                  "sha256": "7329e4bdb82b34969facab387754bd2b365ffb488c53661c206685bed351d260"},
+            "O": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
+                  "sha256": "7c09984a20f76ed5ee118323bffebc5ed6292e998621b503b72299cb17594d2c"},
+            "R": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
+                  "sha256": ""},
+        },
+        "per_layer": [
+            {"F": 4729651, "S": 2794341, "O": 8134309, "R": None},
+            {"F": 21239768, "S": 18388963, "O": 27282265, "R": None},
+            {"F": 21239786, "S": 18388963, "O": 27281204, "R": None},
+            {"F": 21239860, "S": 18389036, "O": 27273763, "R": None},
+            {"F": 21239695, "S": 18388963, "O": 27277292, "R": None},
+            {"F": 21240061, "S": 18388963, "O": 27282448, "R": None},
+            {"F": 21239860, "S": 18388963, "O": 27283892, "R": None},
+            {"F": 40111397, "S": 35688562, "O": 48275817, "R": None},
+            {"F": 19040913, "S": 17602779, "O": 22390790, "R": None},
+            {"F": 19040767, "S": 17602596, "O": 22390735, "R": None},
+            {"F": 19040986, "S": 17602742, "O": 22392728, "R": None},
+            {"F": 19040694, "S": 17602596, "O": 22391869, "R": None},
+            {"F": 19040895, "S": 17602596, "O": 22391869, "R": None},
+            {"F": 36864052, "S": 34641103, "O": 41295020, "R": None},
+            {"F": 17950471, "S": 17209413, "O": 19837153, "R": None},
+            {"F": 17950380, "S": 17209413, "O": 19839566, "R": None},
+            {"F": 17950490, "S": 17209413, "O": 19839310, "R": None},
+            {"F": 17950581, "S": 17209559, "O": 19838469, "R": None},
+            {"F": 17950234, "S": 17209267, "O": 19837975, "R": None},
+            {"F": None, "S": 704441, "O": 2245792, "R": None},
+        ]},
+    "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h'],
+                "sha256": "49292b8e7dd98223913862ab1c3c1ae2c3e9afcbc77088f7fd93d3c857110c67",
+                "bytes_per_launch": 2833849},
 }
 
 
-def pmc_traffic(kind, plan=None):
+def pmc_traffic(kind, plan=None, only=None):
     """Counter-measured HBM bytes per launch, or None once a measured source has changed.  For a
-    per-layer table, `plan` gives the MAC form of each layer (F fused, S split) and the result is
-    the mean over the layers; None if a layer ran in a form the table has no entry for."""
+    per-layer table, `plan` gives the form of each layer (O / R one launch, F fused, S split: the
+    launch that carries the MAC) and the result is the mean over the layers `only` selects (all
+    by default); None if a selected layer ran in a form the table has no entry for."""
     import hashlib
+
+    def fresh(r):
+        h = hashlib.sha256()
+        for src in r["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        return h.hexdigest() == r["sha256"]
+
     rec = PMC_TRAFFIC.get(kind)
     if rec is None:
         return None
-    h = hashlib.sha256()
-    for src in rec["sources"]:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec["sha256"]:
-        return None
     if "per_layer" not in rec:
-        return rec["bytes_per_launch"]
+        return rec["bytes_per_launch"] if fresh(rec) else None
     table = rec["per_layer"]
-    if plan is None or len(plan) != len(table) or any(row.get(c) is None for c, row in zip(plan, table)):
+    if plan is None or len(plan) != len(table):
         return None
-    return round(sum(row[c] for c, row in zip(plan, table)) / len(table))
+    sel = [k for k in range(len(table)) if only is None or only[k]]
+    if not sel or any(table[k].get(plan[k]) is None for k in sel):
+        return None
+    if not all(fresh(rec["forms"][c]) for c in {plan[k] for k in sel}):
+        return None
+    return round(sum(table[k][plan[k]] for k in sel) / len(sel))
 
 
 def log(*a):
@@ -164,12 +196,13 @@ class Stack:
         return sum(B for _, B, _, _, _ in self.steps)
 
     def mac_plan(self, he):
-        """Which launch carries each layer's MAC: 'one' (the whole layer in one launch), 'fused'
+        """Which launch carries each layer's MAC: 'one' / 'rows' (the whole layer in one launch:
+        work items of sub-blocks, chunks and tails / one MAC + inverse item per output row), 'fused'
         (MAC + residue-class tail in one launch, after a forward-transform launch) or 'split' (MAC
         launch, then tail / inverse launch), read from the kernel kinds one call of the layer
         records."""
         plan = []
-        kinds = he.HE_K_MAC | he.HE_K_MAC_TAIL | he.HE_K_LAYER
+        kinds = he.HE_K_MAC | he.HE_K_MAC_TAIL | he.HE_K_LAYER | he.HE_K_LAYER_ROWS
         for ly, B, c0, sh, shn in self.steps:
             self.ctx.profile_reset()
             self.ctx.profile_enable(kinds)
@@ -178,9 +211,10 @@ class Stack:
             else:
                 self.ctx.fc_layer(ly, c0, sh, shn)
             one = self.ctx.profile_read(he.HE_K_LAYER)[0] > 0
+            rows = self.ctx.profile_read(he.HE_K_LAYER_ROWS)[0] > 0
             fused = self.ctx.profile_read(he.HE_K_MAC_TAIL)[0] > 0
             self.ctx.profile_enable(0)
-            plan.append("one" if one else ("fused" if fused else "split"))
+            plan.append("one" if one else ("rows" if rows else ("fused" if fused else "split")))
         self.ctx.profile_reset()
         return plan
 
@@ -222,25 +256,29 @@ class Stack:
                 tot += B * rows * L * i.n_o_p * 4 + (B * rows * i.n_o_p * 4 if shn is not None else 0)
         return tot
 
-    def fwd_bytes(self):
+    def fwd_bytes(self, only=None):
         """Algorithmic HBM bytes of one pass's forward transforms: each c0 row read and written per
         limb; each sh row read once and written for every limb."""
         L, N = self.ctx.L, self.ctx.N
         tot = 0
-        for ly, B, c0, sh, shn in self.steps:
+        for k, (ly, B, c0, sh, shn) in enumerate(self.steps):
+            if only is not None and not only[k]:
+                continue
             rows = B * ly.info.K_in
             tot += rows * L * N * 8
             if sh is not None:
                 tot += rows * N * 4 + rows * L * N * 4
         return tot
 
-    def inverse_bytes(self):
+    def inverse_bytes(self, only=None):
         """Algorithmic HBM bytes of one pass's inverse launches: the MAC output read (block sums
         of every channel, or full rows for FC and full-form conv), sh' read once per output
         polynomial, the output polynomials (FC: their n_o' kept coefficients) written."""
         L, N = self.ctx.L, self.ctx.N
         tot = 0
-        for (ly, B, c0, sh, shn), rows in zip(self.steps, self.rows):
+        for k, ((ly, B, c0, sh, shn), rows) in enumerate(zip(self.steps, self.rows)):
+            if only is not None and not only[k]:
+                continue
             i = ly.info
             if ly.kind == 0:
                 per = N // i.s if i.flags == 0 else N
@@ -262,21 +300,25 @@ class Stack:
             tot += B * ly.info.K_in * L * (2 if sh is not None else 1) * per_row
         return tot
 
-    def tail_butterflies(self):
+    def tail_butterflies(self, only=None):
         """Inverse-transform butterflies of one pass: the (N/s)-point residue-class inverse of
         every real output channel (conv), the N-point inverse of every row block (FC)."""
         L, N = self.ctx.L, self.ctx.N
         tot = 0
-        for (ly, B, c0, sh, shn), rows in zip(self.steps, self.rows):
+        for k, ((ly, B, c0, sh, shn), rows) in enumerate(zip(self.steps, self.rows)):
+            if only is not None and not only[k]:
+                continue
             M = N // ly.info.s if ly.kind == 0 and ly.info.flags == 0 else N
             tot += B * rows * L * (M // 2) * (M.bit_length() - 1)
         return tot
 
-    def modmuls(self):
+    def modmuls(self, only=None):
         """Coefficient-wise modular multiplications of the MAC in one pass."""
         tot = 0
         L, N = self.ctx.L, self.ctx.N
-        for (ly, B, c0, sh, shn), c_o in zip(self.steps, self.rows):
+        for k, ((ly, B, c0, sh, shn), c_o) in enumerate(zip(self.steps, self.rows)):
+            if only is not None and not only[k]:
+                continue
             J = ly.info.K_in * (2 if sh is not None else 1)
             tot += B * J * c_o * L * N
         return tot
@@ -305,10 +347,11 @@ def batched_rooflines(he, ctx, st, stream, sync, passes=2, plan=None):
     """Per-kind kernel time of eager passes over a batched stack (HIP events on the launch
     stream), against the integer roofs: forward and inverse butterflies against the measured
     butterfly rate, MAC products against the 64-bit multiply-add rate.  Each kind also gets its
-    algorithmic HBM bytes per pass over its time as a fraction of HBM (`hbm_frac`)."""
+    algorithmic HBM bytes per pass over its time as a fraction of HBM (`hbm_frac`).  Layers the
+    tuner put in a one-launch form (`plan`) are reported apart, against HBM."""
     import torch
     kinds = [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL), ("intt", he.HE_K_INTT),
-             ("mac_tail", he.HE_K_MAC_TAIL)]
+             ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER), ("layer_rows", he.HE_K_LAYER_ROWS)]
     ctx.profile_reset()
     ctx.profile_enable(sum(k for _, k in kinds))
     with torch.cuda.stream(stream):
@@ -322,26 +365,102 @@ def batched_rooflines(he, ctx, st, stream, sync, passes=2, plan=None):
     ctx.profile_enable(0)
     ctx.profile_reset()
     out = {}
-    fwd_rate = st.butterflies_fwd() / (ms["ntt_fwd"] / 1e3) / 1e9 if ms["ntt_fwd"] else None
+    one = [p in ("one", "rows") for p in plan] if plan is not None else [False] * len(st.steps)
+    multi = [not o for o in one]
+
     def hbm(nbytes, t_ms):
         gbs = nbytes / (t_ms / 1e3) / 1e9
         return {"hbm_bytes_per_batch": int(nbytes), "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
-    out["ntt_fwd"] = {"ms_per_batch": round(ms["ntt_fwd"], 3), "bound": "alu", "achieved": round(fwd_rate, 1),
-                      "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(fwd_rate / BFLY_PEAK_G, 4),
-                      **hbm(st.fwd_bytes(), ms["ntt_fwd"])}
+    if ms["ntt_fwd"]:
+        fwd_rate = st.butterflies_fwd(multi) / (ms["ntt_fwd"] / 1e3) / 1e9
+        out["ntt_fwd"] = {"ms_per_batch": round(ms["ntt_fwd"], 3), "bound": "alu", "achieved": round(fwd_rate, 1),
+                          "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(fwd_rate / BFLY_PEAK_G, 4),
+                          **hbm(st.fwd_bytes(multi), ms["ntt_fwd"])}
     mac_ms = ms["mac"] + ms["mac_tail"]
-    mac_rate = st.modmuls() / (mac_ms / 1e3) / 1e9
-    out["mac"] = {"ms_per_batch": round(mac_ms, 3), "bound": "alu", "achieved": round(mac_rate, 1),
-                  "peak": MAD64_PEAK_G, "unit": "Gmodmul/s", "frac": round(mac_rate / MAD64_PEAK_G, 4)}
-    if plan is not None:
-        out["mac"].update(hbm(st.mac_kernel_bytes(plan), mac_ms))
+    if mac_ms:
+        mac_rate = st.modmuls(multi) / (mac_ms / 1e3) / 1e9
+        out["mac"] = {"ms_per_batch": round(mac_ms, 3), "bound": "alu", "achieved": round(mac_rate, 1),
+                      "peak": MAD64_PEAK_G, "unit": "Gmodmul/s", "frac": round(mac_rate / MAD64_PEAK_G, 4)}
+        if plan is not None:
+            out["mac"].update(hbm(st.mac_kernel_bytes(plan, only=multi), mac_ms))
     inv_ms = ms["tail"] + ms["intt"]
     if inv_ms:
-        inv_rate = st.tail_butterflies() / (inv_ms / 1e3) / 1e9
+        inv_rate = st.tail_butterflies(multi) / (inv_ms / 1e3) / 1e9
         out["inverse"] = {"ms_per_batch": round(inv_ms, 3), "bound": "alu", "achieved": round(inv_rate, 1),
-                          "peak": BFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(inv_rate / BFLY_PEAK_G, 4),
-                          **hbm(st.inverse_bytes(), inv_ms)}
+                          "peak": GSBFLY_PEAK_G, "unit": "Gbutterfly/s", "frac": round(inv_rate / GSBFLY_PEAK_G, 4),
+                          **hbm(st.inverse_bytes(multi), inv_ms)}
+    lay_ms = ms["layer"] + ms["layer_rows"]
+    if lay_ms:
+        out["one_launch_layers"] = {"ms_per_batch": round(lay_ms, 3), "layers": sum(one),
+                                    **hbm(st.layer_bytes(one), lay_ms)}
+    return out
+
+
+def grouped_form(he, ctx, args, widths, stream, sync):
+    """The batched stacks of every width resident at once and evaluated by grouped launches
+    (he_group_*): one launch per layer index (the k-th call of every width together), and one
+    launch for every call of every width.  Each pass is the same work as one pass of each width's
+    captured sequence.  Roofline: the algorithmic HBM bytes of a pass (resident operands once per
+    layer, inputs and outputs once) over the grouped launch's own time (HIP events)."""
+    import torch
+    stacks, ctxs = [], {}
+    for width in widths:
+        N, L = (8192, 4) if width < 4 else (16384, 6)
+        if (N, L) not in ctxs:
+            ctxs[(N, L)] = ctx if N == 8192 else he.Context(N, L, wl.T_PLAIN)
+        log(f"setup: grouped x{width} N={N} L={L}")
+        stacks.append(Stack(he, ctxs[(N, L)], wl.CONFIG_BATCHED, width, [10, 100], [32, 32], N, L))
+    sync()
+    per_layer = []
+    for k in range(max(len(st.steps) for st in stacks)):
+        g = he.Group()
+        for st in stacks:
+            if k < len(st.steps):
+                ly, B, c0, sh, shn = st.steps[k]
+                g.add(ly, c0, sh, shn)
+        per_layer.append(g.build())
+    whole = he.Group()
+    for st in stacks:
+        for ly, B, c0, sh, shn in st.steps:
+            whole.add(ly, c0, sh, shn)
+    whole.build()
+    il = sum(st.image_layers() for st in stacks)
+    nbytes = sum(st.layer_bytes() for st in stacks)
+    steps = args.batched_steps
+    out = {"widths": widths, "image_layers_per_pass": il, "algorithmic_bytes_per_pass": int(nbytes)}
+    with torch.cuda.stream(stream):
+        T = time_loop(lambda: [g.run(stream) for g in per_layer], steps, 1, sync)
+    for g in per_layer:
+        g.check(stream)
+    out["per_layer_index"] = {"launches_per_pass": len(per_layer), "layers_per_s": round(il * steps / T, 1),
+                              "ms_per_pass": round(T / steps * 1e3, 3)}
+    with torch.cuda.stream(stream):
+        T = time_loop(lambda: whole.run(stream), steps, 1, sync)
+    whole.check(stream)
+    items, tiled, ws = whole.items()
+    c0ctx = stacks[0].ctx
+    c0ctx.profile_reset()
+    c0ctx.profile_enable(he.HE_K_GROUP)
+    with torch.cuda.stream(stream):
+        time_loop(lambda: whole.run(stream), 3, 0, sync)
+    n, ms = c0ctx.profile_read(he.HE_K_GROUP)
+    c0ctx.profile_enable(0)
+    c0ctx.profile_reset()
+    kern_s = ms / 1e3 / max(1, n)
+    gbs = nbytes / kern_s / 1e9
+    out["one_launch"] = {"launches_per_pass": 1, "calls": len(whole), "layers_per_s": round(il * steps / T, 1),
+                         "ms_per_pass": round(T / steps * 1e3, 3), "items_ntt_mac_inverse": list(items),
+                         "image_tiled_calls": tiled, "workspace_bytes": ws,
+                         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                      "avg_launch_ms": round(kern_s * 1e3, 3), "kernel": "k_fused_group"}}
+    log(f"grouped: {json.dumps(out)}")
+    for g in per_layer:
+        g.free()
+    whole.free()
+    del stacks
+    torch.cuda.empty_cache()
     return out
 
 
@@ -418,7 +537,7 @@ def single_conv_form(he, args, stream, sync):
         stream.synchronize()
         lat.append(time.perf_counter() - t0)
     kinds = [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL), ("intt", he.HE_K_INTT),
-             ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER)]
+             ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER), ("layer_rows", he.HE_K_LAYER_ROWS)]
     ctx.profile_reset()
     ctx.profile_enable(sum(k for _, k in kinds))
     with torch.cuda.stream(stream):
@@ -598,6 +717,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-group", action="store_true", help="skip the grouped launches of the batched form")
     ap.add_argument("--batched-widths", default="1,2,4", help="plain-20 widths of the batched form")
     ap.add_argument("--no-resnet50", action="store_true",
                     help="skip the ResNet-50-shaped layers (each distinct shape packed and timed in turn)")
@@ -615,13 +735,15 @@ def main():
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--stress-clients", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-rates", action="store_true",
+                    help="keep the stored integer-ALU roofs instead of measuring them (he_probe_rate)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="also run one 256 MiB device-to-device copy (known bytes) for counter calibration")
-    ap.add_argument("--pmc-mac-form", choices=["F", "S", "O"], default=None,
+    ap.add_argument("--pmc-mac-form", choices=["F", "S", "O", "R"], default=None,
                     help="counter runs: pin every layer of the plain stack to the fused (F) or split (S) MAC "
-                         "form or the one-launch layer (O), run only the plain loop and print the plan (the "
-                         "per-layer traffic table)")
+                         "form or a one-launch form (O work items, R rows; the FC head takes O), run only the "
+                         "plain loop and print the plan (the per-layer traffic table)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards across GPUs by "
@@ -635,6 +757,14 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     sync = torch.cuda.synchronize
+    rates = None
+    if not args.no_rates:
+        global BFLY_PEAK_G, GSBFLY_PEAK_G, MAD64_PEAK_G
+        rates = alu_rates(he)
+        BFLY_PEAK_G = rates["butterfly_ct"]["G_per_s"]
+        GSBFLY_PEAK_G = rates["butterfly_gs"]["G_per_s"]
+        MAD64_PEAK_G = rates["mad_u64_u32"]["G_per_s"]
+        log(f"alu rates: {json.dumps(rates)}")
 
     # ---------------- plain x1 stack, one image per call
     log("setup: x1 stack N=8192 L=4")
@@ -642,7 +772,7 @@ def main():
     st = Stack(he, ctx, wl.CONFIG_PLAIN20_X1, 1, [10], [1], 8192, 4)
     n_layers = len(st.steps)
     if args.pmc_mac_form is not None:
-        ctx.tune_force(he.HE_TUNE_MAC, {"F": 2, "S": 0, "O": 7}[args.pmc_mac_form])
+        ctx.tune_force(he.HE_TUNE_MAC, {"F": 2, "S": 0, "O": 7, "R": 8}[args.pmc_mac_form])
     elif not args.no_tune:
         st.autotune()
     sync()
@@ -660,7 +790,7 @@ def main():
     log(f"plain: {T_plain / args.steps * 1e3:.3f} ms/step")
     if args.pmc_mac_form is not None:
         # layer order of the MAC launches above is the stack order, one per layer per call
-        plan = "".join({"one": "O", "fused": "F", "split": "S"}[p] for p in st.mac_plan(he))
+        plan = "".join({"one": "O", "rows": "R", "fused": "F", "split": "S"}[p] for p in st.mac_plan(he))
         print(json.dumps({"pmc_mac_form": args.pmc_mac_form, "plan": plan,
                           "calls": args.warmup + args.steps + 1}), flush=True)
         return
@@ -668,12 +798,14 @@ def main():
     # kernel timing of the same calls (HIP events on the launch stream)
     plan = st.mac_plan(he)
     ctx.profile_reset()
-    ctx.profile_enable(he.HE_K_MAC | he.HE_K_NTT_FWD | he.HE_K_TAIL | he.HE_K_INTT | he.HE_K_MAC_TAIL | he.HE_K_LAYER)
+    ctx.profile_enable(he.HE_K_MAC | he.HE_K_NTT_FWD | he.HE_K_TAIL | he.HE_K_INTT | he.HE_K_MAC_TAIL | he.HE_K_LAYER |
+                       he.HE_K_LAYER_ROWS)
     with torch.cuda.stream(stream):
         T_prof = time_loop(lambda: st.seq.run(stream), args.steps, 0, sync)
     kern = {}
     for name, kind in [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL),
-                       ("intt", he.HE_K_INTT), ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER)]:
+                       ("intt", he.HE_K_INTT), ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER),
+                       ("layer_rows", he.HE_K_LAYER_ROWS)]:
         n, ms = ctx.profile_read(kind)
         kern[name] = {"launches": n, "total_ms": ms, "avg_us": (ms * 1e3 / n) if n else None}
     ctx.profile_enable(0)
@@ -717,23 +849,27 @@ def main():
     # split MAC (FC head, and any layer the tuner gave the two-launch form)
     rooflines = {}
     per_step = {}
-    plan_letters = "".join({"one": "O", "fused": "F", "split": "S"}[p] for p in plan)
-    n_one = plan.count("one")
-    if kern["layer"]["launches"]:
+    plan_letters = "".join({"one": "O", "rows": "R", "fused": "F", "split": "S"}[p] for p in plan)
+    one_sel = [p in ("one", "rows") for p in plan]
+    n_one = sum(one_sel)
+    lay_n = kern["layer"]["launches"] + kern["layer_rows"]["launches"]
+    if lay_n:
         # whole layers in one launch (forward transforms, MAC, inverse, extraction)
-        one_bytes = st.layer_bytes(only=[p == "one" for p in plan])
-        lay_avg_s = kern["layer"]["total_ms"] / 1e3 / kern["layer"]["launches"]
+        one_bytes = st.layer_bytes(only=one_sel)
+        lay_ms = kern["layer"]["total_ms"] + kern["layer_rows"]["total_ms"]
+        lay_avg_s = lay_ms / 1e3 / lay_n
         ach = one_bytes / n_one / lay_avg_s / 1e9
         rooflines["layer"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("layer", plan_letters),
+                              "frac": round(ach / HBM_PEAK_GBS, 4),
+                              "traffic": pmc_traffic("layers", plan_letters, one_sel),
                               "algorithmic_bytes_per_launch": one_bytes // n_one,
-                              "kernel": f"k_fused_layer (forward NTT, MAC, residue-class / prefix inverse and "
-                                        f"extraction in one launch, {n_one} layers)",
+                              "kernel": f"k_fused_layer / k_fused_rows (forward NTT, MAC, residue-class / prefix "
+                                        f"inverse and extraction in one launch, {n_one} layers)",
                               "launches_per_step": n_one, "avg_launch_us": round(lay_avg_s * 1e6, 3)}
-        per_step["layer"] = kern["layer"]["total_ms"]
+        per_step["layer"] = lay_ms
     mac_n = kern["mac"]["launches"] + kern["mac_tail"]["launches"]
     if mac_n:
-        multi = [p != "one" for p in plan]
+        multi = [not o for o in one_sel]
         n_multi = sum(multi)
         mac_bytes = st.mac_kernel_bytes(plan, only=multi)
         mac_ms = kern["mac"]["total_ms"] + kern["mac_tail"]["total_ms"]
@@ -742,14 +878,14 @@ def main():
         n_fused = plan.count("fused")
         rooflines["mac"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(achieved / HBM_PEAK_GBS, 4),
-                            "traffic": pmc_traffic("mac", plan_letters), "mac_forms": plan_letters,
+                            "traffic": pmc_traffic("layers", plan_letters, multi), "mac_forms": plan_letters,
                             "algorithmic_bytes_per_launch": mac_bytes // n_multi,
                             "kernel": f"k_mac_tail (fused MAC + residue-class inverse, {n_fused} layers) / "
                                       f"k_mac_class, k_mac_full (split MAC, {n_multi - n_fused} layers)",
                             "launches_per_step": n_multi, "avg_launch_us": round(mac_avg_s * 1e6, 3)}
         per_step["mac"] = mac_ms
     if kern["ntt_fwd"]["launches"]:
-        multi = [p != "one" for p in plan]
+        multi = [not o for o in one_sel]
         fwd_avg_s = kern["ntt_fwd"]["total_ms"] / 1e3 / kern["ntt_fwd"]["launches"]
         fwd_bfly = st.butterflies_fwd(only=multi) / sum(multi)        # one forward launch per layer
         fwd_g = fwd_bfly / fwd_avg_s / 1e9
@@ -784,6 +920,7 @@ def main():
         "limb_poly_macs_per_s": round(st.modmuls() / 8192 * args.steps / T_plain, 1),
         "roofline": roofline,
         "rooflines": rooflines,
+        "alu_rates": rates,
         "layer_forms": plan_letters,
         "dominant_kernel": dominant,
         "kernels": kern,
@@ -843,6 +980,8 @@ def main():
             del bseq, bst
             torch.cuda.empty_cache()
         bres["all_widths_layers_per_s"] = round(tot_layers / tot_time, 1)
+        if not args.no_group:
+            bres["grouped"] = grouped_form(he, ctx, args, widths, stream, sync)
         result["forms"]["batched"] = bres
 
     # ---------------- served: Poisson stream of single-layer requests, 128 clients

@@ -270,9 +270,12 @@ int he_poly_mul(he_ctx *ctx, uint32_t rows, const uint32_t *d_a, const uint32_t 
  * class inverse + extraction), HE_K_INTT (full inverse + extraction),
  * HE_K_MAC_TAIL (MAC, residue-class inverse and extraction in one launch),
  * HE_K_LAYER (the whole layer in one launch: forward transforms, MAC, inverse
- * and extraction).
+ * and extraction), HE_K_LAYER_ROWS (the same with one MAC + inverse item per
+ * output row), HE_K_GROUP (a grouped launch, he_group_run; recorded on the
+ * context of the group's first call).
  */
-enum { HE_K_NTT_FWD = 1, HE_K_MAC = 2, HE_K_TAIL = 4, HE_K_INTT = 8, HE_K_MAC_TAIL = 16, HE_K_LAYER = 32 };
+enum { HE_K_NTT_FWD = 1, HE_K_MAC = 2, HE_K_TAIL = 4, HE_K_INTT = 8, HE_K_MAC_TAIL = 16, HE_K_LAYER = 32,
+       HE_K_LAYER_ROWS = 64, HE_K_GROUP = 128 };
 int he_profile_enable(he_ctx *ctx, uint32_t kind_mask);
 int he_profile_read(he_ctx *ctx, uint32_t kind, uint64_t *launches, double *total_ms);
 int he_profile_reset(he_ctx *ctx);
@@ -338,6 +341,54 @@ int he_seq_capture(he_seq *seq, void *stream);
 int he_seq_replay(he_seq *seq, void *stream);
 uint32_t he_seq_length(const he_seq *seq);
 void he_seq_free(he_seq *seq);
+
+/*
+ * Grouped launch: independent layer calls -- any layers, contexts (ring
+ * degrees, limb counts) and batch sizes on one device -- evaluated by ONE
+ * kernel launch.  Each call is the server evaluation of he_conv_layer /
+ * he_fc_layer (Alg. 1 / Alg. 2, with the NTT-domain products of Sec. IV-A-1)
+ * and gives the same output words.  The launch walks a device-side list of
+ * work items: forward-transform sub-blocks of every call, then MAC items
+ * (image x channel tiles of one limb and slot range for batched conv calls,
+ * so that a resident operand word is read once per tile of images), then the
+ * residue-class inverse and extraction items; an item waits, through counters,
+ * only for the items of its own call that it reads.
+ *
+ * he_layer_call: one call, arguments as he_conv_layer / he_fc_layer (the kind
+ * is the layer's).  Conv layers must be packed in the residue-class form with
+ * 2 <= s <= 256 and N/s <= 4096; FC layers need n_o' <= 1024; N is 4096,
+ * 8192 or 16384 (HE_EUNSUPPORTED otherwise, naming the call).
+ *
+ * he_group_create -- plans the items, allocates the group's device job list,
+ * workspace (he_layer_workspace_bytes of every call) and zeroed counters, and
+ * uploads the list (synchronous).  The buffers of the calls are baked in: they
+ * must stay valid, and keep their sizes, while the group exists.  flags:
+ * HE_GROUP_MAC_AUTO (image tiles for conv calls of B >= 4), HE_GROUP_MAC_PER_IMAGE
+ * (one image per MAC item), HE_GROUP_MAC_TILED (image tiles wherever the shape
+ * allows).  *out = NULL on failure.
+ * he_group_run -- one launch on `stream`; allocates nothing (it may be
+ * captured into a HIP graph).  The counters return to zero by the end of each
+ * launch; launches of one group must not overlap (one stream at a time).
+ * he_group_check -- synchronises the stream; HE_EDEVICE if an item of an earlier
+ * launch gave up waiting (about a second; its call's words are then undefined;
+ * the flag is cleared), else HE_OK.
+ * he_group_items -- work items per phase (NTT, MAC, inverse), the number of
+ * calls whose MAC runs in image tiles, and the workspace bytes.
+ */
+typedef struct {
+    he_ctx *ctx;
+    const he_layer *layer;
+    uint32_t B;
+    const uint32_t *d_c0, *d_sh, *d_sh_next;
+    uint32_t *d_out;
+} he_layer_call;
+typedef struct he_group he_group;
+enum { HE_GROUP_MAC_AUTO = 0, HE_GROUP_MAC_PER_IMAGE = 1, HE_GROUP_MAC_TILED = 2 };
+int he_group_create(const he_layer_call *calls, uint32_t n, uint32_t flags, he_group **out);
+int he_group_run(he_group *g, void *stream);
+int he_group_check(he_group *g, void *stream);
+int he_group_items(const he_group *g, uint32_t *items, uint32_t *tiled_jobs, size_t *workspace_bytes);
+void he_group_free(he_group *g);
 
 /*
  * Serving runtime: continuous batching of layer requests (the server of Alg. 1
@@ -420,6 +471,21 @@ enum { HE_TUNE_NTT_FWD = 1, HE_TUNE_NTT_INV = 2, HE_TUNE_TAIL = 3, HE_TUNE_MAC =
 int he_tune_force(he_ctx *ctx, uint32_t knob, int32_t value);
 int he_autotune_layer(he_ctx *ctx, const he_layer *layer, uint32_t B, void *stream);
 int he_tune_get(he_ctx *ctx, uint32_t knob, uint32_t key_size, uint32_t key_rows, int32_t *value);
+
+/*
+ * he_probe_rate -- measurement aid for the integer-ALU roofs: the whole chip's
+ * throughput of one instruction mix with no memory traffic (eight 256-thread
+ * workgroups per CU, 8 independent chains per thread, `iters` rounds).  Kinds:
+ * HE_PROBE_BFLY / HE_PROBE_GSBFLY (the forward / inverse Shoup butterflies of
+ * the NTT kernels, per butterfly), HE_PROBE_MAD64 (32x32 -> 64-bit
+ * multiply-add of the MAC), HE_PROBE_ADD, HE_PROBE_MULLO, HE_PROBE_MULHI (one
+ * 32-bit vector instruction each).  *ops_per_s: operations per second; *ms
+ * (may be NULL): the timed launch.  Runs on the current device and the null
+ * stream, synchronises.
+ */
+enum { HE_PROBE_BFLY = 1, HE_PROBE_GSBFLY = 2, HE_PROBE_MAD64 = 3, HE_PROBE_ADD = 4, HE_PROBE_MULLO = 5,
+       HE_PROBE_MULHI = 6 };
+int he_probe_rate(uint32_t kind, uint32_t iters, double *ops_per_s, double *ms);
 
 void he_free_layer(he_layer *layer);
 void he_free(he_ctx *ctx);

@@ -28,7 +28,7 @@ _lib = None
 
 def build() -> str:
     """Compile oracle/c/he_oracle.c into oracle/c/liboracle.so (gcc -O2 -fopenmp)."""
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.{os.getpid()}.tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", tmp, SRC]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

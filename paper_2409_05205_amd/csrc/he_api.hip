@@ -19,6 +19,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <memory>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -278,12 +279,10 @@ bool mac_lds_ok(const he_layer *ly, uint32_t B) {
     return B >= 2 && in.kind == HE_LAYER_CONV && in.flags == HE_PACK_CLASS_INTT && in.s >= 2 && in.N >= 256;
 }
 
-// The one-launch layer form (kernels_fused.hip) for this layer at batch B: its item geometry
-// in *jb when the shape allows it.  Its MAC reads the resident operands once per image, so
-// the automatic rule keeps it for B = 1.
-bool layer_one_launch_ok(const he_ctx *ctx, const he_layer *ly, uint32_t B, FusedLayer *jb, bool rows = false) {
+// The item geometry of this layer at batch B in the one-launch / grouped forms (kernels_fused.hip),
+// before the plan, in f; false when the shape is outside them.
+bool fused_layer_shape(const he_ctx *ctx, const he_layer *ly, uint32_t B, bool rows, FusedLayer &f) {
     const he_layer_info &in = ly->info;
-    FusedLayer f;
     std::memset(&f, 0, sizeof(f));
     f.kind = in.kind == HE_LAYER_CONV ? FZ_KIND_CONV : FZ_KIND_FC;
     if (in.kind == HE_LAYER_CONV && in.flags != HE_PACK_CLASS_INTT) return false;
@@ -301,6 +300,15 @@ bool layer_one_launch_ok(const he_ctx *ctx, const he_layer *ly, uint32_t B, Fuse
     f.rows_form = rows ? 1u : 0u;
     if (!fused_layer_ok(f)) return false;
     f.ntt_c0 = f.ntt_sh = in.K_in;
+    return true;
+}
+
+// The one-launch layer form for this layer at batch B: its item geometry in *jb when the shape
+// allows it and its counters fit a sync block.  Its MAC reads the resident operands once per
+// image, so the automatic rule keeps it for B = 1.
+bool layer_one_launch_ok(const he_ctx *ctx, const he_layer *ly, uint32_t B, FusedLayer *jb, bool rows = false) {
+    FusedLayer f;
+    if (!fused_layer_shape(ctx, ly, B, rows, f)) return false;
     if (FZ_SB_HDR + fused_layer_plan(f) > FZ_SYNC_WORDS) return false;
     if (jb) *jb = f;
     return true;
@@ -1374,7 +1382,7 @@ int layer_exec(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *d_c0
         jb.ntt_c0 = x_given ? 0 : jb.K_in;
         jb.ntt_sh = (x_given || !d_sh) ? 0 : jb.K_in;
         fused_layer_plan(jb);
-        ProfScope ps(ctx, HE_K_LAYER);
+        ProfScope ps(ctx, form == 8 ? HE_K_LAYER_ROWS : HE_K_LAYER);
         hipError_t e = launch_fused_layer(jb, ctx->tw, ctx->twsh, ctx->twi, ctx->twish, ctx->xinv, ctx->lc, sync,
                                           st, ps.ev());
         if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, conv ? "conv layer launch" : "fc layer launch");
@@ -1569,5 +1577,172 @@ int he_poly_mul(he_ctx *ctx, uint32_t rows, const uint32_t *d_a, const uint32_t 
     if (e != hipSuccess) return dev_fail(e, "pointwise");
     return he_ntt_inverse(ctx, rows, A, d_c, stream);
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ grouped launch
+struct he_group {
+    int device = 0;
+    he_ctx *ctx0 = nullptr;              // the first call's context: timing (he_profile_*)
+    std::vector<FusedJob> jobs;          // host copy of the device job list
+    FusedJob *d_jobs = nullptr;
+    LimbConsts *d_lc = nullptr;          // one per distinct context
+    void *ws = nullptr;                  // every job's NTT-domain inputs and block sums
+    uint32_t *sync = nullptr;            // header + every job's counters, zero between launches
+    size_t ws_bytes = 0, sync_words = 0;
+    uint32_t count[3] = {0, 0, 0};
+};
+
+namespace {
+
+void group_release(he_group *g) {
+    if (!g) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(g->device);
+    if (g->d_jobs) (void)hipFree(g->d_jobs);
+    if (g->d_lc) (void)hipFree(g->d_lc);
+    if (g->ws) (void)hipFree(g->ws);
+    if (g->sync) (void)hipFree(g->sync);
+    (void)hipSetDevice(cur);
+    delete g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int he_group_create(const he_layer_call *calls, uint32_t n, uint32_t flags, he_group **out) {
+    if (!out || !calls || n == 0 || flags > HE_GROUP_MAC_TILED) return HE_EINVAL;
+    *out = nullptr;
+    std::unique_ptr<he_group, void (*)(he_group *)> g(new he_group, group_release);
+    g->ctx0 = calls[0].ctx;
+    if (!g->ctx0) return HE_EINVAL;
+    g->device = g->ctx0->device;
+    std::vector<he_ctx *> ctxs;
+    std::vector<size_t> ws_off(n);
+    size_t ws_total = 0, ctr_total = 0;
+    g->jobs.resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const he_layer_call &c = calls[i];
+        if (!c.ctx || c.ctx->device != g->device || !c.layer || c.layer->ctx != c.ctx || c.B == 0) return HE_EINVAL;
+        const int rc = check_layer_args(c.ctx, c.layer, c.layer->info.kind, c.d_c0, c.d_out, c.d_c0);
+        if (rc != HE_OK) return rc;
+        FusedLayer jb;
+        if (!fused_layer_shape(c.ctx, c.layer, c.B, false, jb)) {
+            g_last_error = "he_group_create: call " + std::to_string(i) +
+                           ": layer shape outside the grouped launch (conv in the residue-class form with "
+                           "2 <= s <= 256 and N/s <= 4096, or FC with n_o' <= 1024; N 4096..16384)";
+            return HE_EUNSUPPORTED;
+        }
+        const he_layer_info &in = c.layer->info;
+        jb.c0 = c.d_c0;
+        jb.sh = c.d_sh;
+        jb.sh_next = c.d_sh_next;
+        jb.out = c.d_out;
+        jb.op = c.layer->op;
+        jb.bias = c.layer->bias;
+        jb.Juse = c.d_sh ? jb.Jtot : jb.K_in;
+        jb.ntt_c0 = jb.K_in;
+        jb.ntt_sh = c.d_sh ? jb.K_in : 0;
+        jb.no_wide = 1;
+        // image-tiled MAC items: a resident operand word read once per tile of images rather than
+        // once per image (automatic from four images up)
+        if (jb.kind == FZ_KIND_CONV && flags != HE_GROUP_MAC_PER_IMAGE && (c.B >= 4 || flags == HE_GROUP_MAC_TILED)) {
+            MacLdsGeom gm;
+            size_t lds = 0;
+            if (mac_lds_geometry(c.B, c.layer->n_rows, in.N, in.s, &gm, &lds, 32) && lds <= fused_group_lds_bytes() &&
+                (size_t)gm.R * gm.cpb <= in.N / 4) {
+                jb.mac_tiled = 1;
+                jb.gm = gm;
+            }
+        }
+        fused_layer_plan(jb);
+        jb.ctr_stride = 32;   // one counter per 128-byte line
+        ws_off[i] = ws_total;
+        ws_total += layer_ws_bytes(c.layer, c.B);
+        FusedJob &J = g->jobs[i];
+        std::memset(&J, 0, sizeof(J));
+        J.jb = jb;
+        J.tw = c.ctx->tw;
+        J.twsh = c.ctx->twsh;
+        J.twi = c.ctx->twi;
+        J.twish = c.ctx->twish;
+        J.xinv = c.ctx->xinv;
+        J.ctr_off = (uint32_t)ctr_total;
+        ctr_total += (size_t)jb.n_ctr * jb.ctr_stride;
+        if (ctr_total > (1u << 30)) return HE_EUNSUPPORTED;
+        for (int p = 0; p < 3; ++p) J.first[p] = g->count[p];
+        g->count[0] += jb.n_ntt;
+        g->count[1] += jb.n_mac;
+        g->count[2] += jb.n_inv;
+        if (std::find(ctxs.begin(), ctxs.end(), c.ctx) == ctxs.end()) ctxs.push_back(c.ctx);
+    }
+    for (int p = 0; p < 3; ++p)
+        if (g->count[p] > (1u << 28)) return HE_EUNSUPPORTED;
+    int cur = 0;
+    HE_HIP(hipGetDevice(&cur));
+    HE_HIP(hipSetDevice(g->device));
+    struct Restore {
+        int d;
+        ~Restore() { (void)hipSetDevice(d); }
+    } restore{cur};
+    g->ws_bytes = align256(ws_total > 0 ? ws_total : 256);
+    g->sync_words = FZ_SB_HDR + ctr_total;
+    if (hipMalloc(&g->ws, g->ws_bytes) != hipSuccess || hipMalloc((void **)&g->sync, g->sync_words * 4) != hipSuccess ||
+        hipMalloc((void **)&g->d_lc, ctxs.size() * sizeof(LimbConsts)) != hipSuccess ||
+        hipMalloc((void **)&g->d_jobs, n * sizeof(FusedJob)) != hipSuccess) {
+        g_last_error = "he_group_create: out of device memory";
+        return HE_ENOMEM;
+    }
+    HE_HIP(hipMemset(g->sync, 0, g->sync_words * 4));
+    for (size_t k = 0; k < ctxs.size(); ++k)
+        HE_HIP(hipMemcpy(g->d_lc + k, &ctxs[k]->lc, sizeof(LimbConsts), hipMemcpyHostToDevice));
+    for (uint32_t i = 0; i < n; ++i) {
+        FusedJob &J = g->jobs[i];
+        const size_t k = std::find(ctxs.begin(), ctxs.end(), calls[i].ctx) - ctxs.begin();
+        J.lc = g->d_lc + k;
+        J.jb.x = (uint32_t *)((char *)g->ws + ws_off[i]);
+        J.jb.h = (uint32_t *)((char *)g->ws + ws_off[i] + x_bytes(calls[i].layer, calls[i].B));
+    }
+    HE_HIP(hipMemcpy(g->d_jobs, g->jobs.data(), n * sizeof(FusedJob), hipMemcpyHostToDevice));
+    *out = g.release();
+    return HE_OK;
+}
+
+int he_group_run(he_group *g, void *stream) {
+    if (!g) return HE_EINVAL;
+    ProfScope ps(g->ctx0, HE_K_GROUP);
+    hipError_t e = launch_fused_group(g->d_jobs, (uint32_t)g->jobs.size(), g->count, g->sync, (hipStream_t)stream,
+                                      ps.ev());
+    if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "grouped layer launch");
+    return HE_OK;
+}
+
+int he_group_check(he_group *g, void *stream) {
+    if (!g) return HE_EINVAL;
+    HE_HIP(hipStreamSynchronize((hipStream_t)stream));
+    uint32_t err = 0;
+    HE_HIP(hipMemcpy(&err, g->sync + FZ_SB_ERR, 4, hipMemcpyDeviceToHost));
+    if (err == 0) return HE_OK;
+    HE_HIP(hipMemset(g->sync + FZ_SB_ERR, 0, 4));
+    g_last_error = "a grouped launch gave up waiting for an item it depends on";
+    return HE_EDEVICE;
+}
+
+int he_group_items(const he_group *g, uint32_t *items, uint32_t *tiled_jobs, size_t *workspace_bytes) {
+    if (!g) return HE_EINVAL;
+    if (items)
+        for (int p = 0; p < 3; ++p) items[p] = g->count[p];
+    if (tiled_jobs) {
+        uint32_t k = 0;
+        for (const FusedJob &J : g->jobs) k += J.jb.mac_tiled ? 1u : 0u;
+        *tiled_jobs = k;
+    }
+    if (workspace_bytes) *workspace_bytes = g->ws_bytes;
+    return HE_OK;
+}
+
+void he_group_free(he_group *g) { group_release(g); }
 
 }  // extern "C"

@@ -149,8 +149,13 @@ struct FusedLayer {
     uint32_t ntt_c0, ntt_sh;  // input rows per image transformed in this launch (K_in or 0 each)
     uint32_t rows_form;       // conv: 1 = whole-row NTT items and one MAC + tail item per output row
                               // (1024-thread workgroups); 0 = sub-block NTT, MAC chunk and tail items
-    // filled by fused_layer_plan
-    uint32_t ng, mac_per_bl, tail_rw, n_ntt, n_mac, n_inv, n_ctr, ctr_stride;
+    uint32_t mac_tiled;       // conv, grouped launch: MAC items are LDS-staged tiles of images x
+                              // channels (geometry gm); 0 = one image per MAC item
+    uint32_t no_wide;         // conv: per-image MAC items by channel groups only (grouped launch)
+    MacLdsGeom gm;
+    // filled by fused_layer_plan.  Counters go per image tile of 2^tile_log images (n_tiles of
+    // them; one image per tile unless the MAC is tiled)
+    uint32_t ng, mac_per_bl, tail_rw, n_ntt, n_mac, n_inv, n_ctr, ctr_stride, tile_log, n_tiles;
 };
 // Whether the one-launch form handles this layer shape (N 4096..16384; conv 2 <= s <= 256 with
 // N/s <= 4096; fc n_o' <= 1024).
@@ -160,6 +165,22 @@ bool fused_layer_ok(const FusedLayer &jb);
 uint32_t fused_layer_plan(FusedLayer &jb);
 hipError_t launch_fused_layer(const FusedLayer &jb, const uint32_t *tw, const uint32_t *twsh, const uint32_t *twi,
                               const uint32_t *twish, const uint32_t *xinv, const LimbConsts &lc, uint32_t *sync,
+                              hipStream_t st, const LaunchEv *ev = nullptr);
+
+// Grouped launch: the work items of several independent layer calls (any contexts, shapes and
+// batch sizes) in one launch, read from a device-side job list.  Each job is a planned
+// FusedLayer (rows_form = 0) with its context's tables and its own counters.
+struct FusedJob {
+    FusedLayer jb;
+    const uint32_t *tw, *twsh, *twi, *twish, *xinv;
+    const LimbConsts *lc;     // device copy of the context's limb constants
+    uint32_t ctr_off;         // the job's counters: words past FZ_SB_HDR of the group's sync block
+    uint32_t first[3];        // first item of the job in each phase (NTT, MAC, tail)
+};
+// Largest LDS need (bytes) of a tiled MAC item the grouped launch accepts.
+uint32_t fused_group_lds_bytes();
+// jobs: device array of n_jobs entries; count[p]: items of phase p over all jobs.
+hipError_t launch_fused_group(const FusedJob *jobs, uint32_t n_jobs, const uint32_t count[3], uint32_t *sync,
                               hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Client masks from the server's resident operands (kernels_client.hip): noise rows into the

@@ -43,6 +43,7 @@
 // chunk shares and adds Delta (d + sh').  No full-length inverse is run.
 
 #include "he_kernels.h"
+#include "mac_device.h"
 #include "ntt_device.h"
 
 namespace {
@@ -118,8 +119,16 @@ __device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const LimbCon
     return reduce64((uint64_t)a * b, c);
 }
 
+// Images of counter tile bt (tiles of 2^tile_log images; the last may be short).
+__device__ __forceinline__ uint32_t fz_tile_imgs(const FusedLayer &jb, uint32_t bt) {
+    const uint32_t first = bt << jb.tile_log, n = 1u << jb.tile_log;
+    return jb.B - first < n ? jb.B - first : n;
+}
+
 // ------------------------------------------------------------------ NTT items
-template <int LOGN>
+// TWB: the workgroup size the twiddle prefetch is sized for (PassTw); a larger value keeps fewer
+// twiddles in registers.
+template <int LOGN, int TWB = FZ_THREADS>
 __device__ __forceinline__ void fz_ntt_item(const FusedLayer &jb, uint32_t it, uint32_t *lds, const uint32_t *__restrict__ tw,
                             const uint32_t *__restrict__ twsh, const LimbConsts &lc, uint32_t *ctr) {
     constexpr int K = 2;
@@ -153,10 +162,10 @@ __device__ __forceinline__ void fz_ntt_item(const FusedLayer &jb, uint32_t it, u
     const uint32_t *Wsh = twsh + (size_t)l * N;
     const uint32_t tb = (1u << K) + sub;
     // twiddles of the leading passes in registers: loads under the operand stream are slow
-    PassTw<LS, LOGR, FZ_THREADS> ptw;
-    fwd_tw_load<LS, LOGR, FZ_THREADS, 0>(ptw, tid, W, Wsh, tb);
+    PassTw<LS, LOGR, TWB> ptw;
+    fwd_tw_load<LS, LOGR, TWB, 0>(ptw, tid, W, Wsh, tb);
     uint32_t v[1 << LOGR];
-    fwd_pass<LS, LOGR, FZ_THREADS, 0, K>(v, ptw, lds, tid, in, W, Wsh, q, q2, tb, sub);
+    fwd_pass<LS, LOGR, TWB, 0, K>(v, ptw, lds, tid, in, W, Wsh, q, q2, tb, sub);
 #pragma unroll
     for (int i = 0; i < (1 << LOGR); ++i) {
         const uint32_t idx = tid + i * T;
@@ -164,10 +173,11 @@ __device__ __forceinline__ void fz_ntt_item(const FusedLayer &jb, uint32_t it, u
         y = csub(y, q2);
         st_dev(out + idx, csub(y, q));
     }
-    fz_signal(ctr + ((b * L + l) * 4u + sub) * jb.ctr_stride, 1u);
+    fz_signal(ctr + (((b >> jb.tile_log) * L + l) * 4u + sub) * jb.ctr_stride, 1u);
 }
 
 // ------------------------------------------------------------------ MAC items (conv)
+// The per-image MAC items below run with one image per counter tile (tile_log = 0).
 // Image b, limb l, slots [c 1024, (c + 1) 1024) (4 per thread), channels [n0, n1).
 __device__ __forceinline__ void fz_mac_conv_item(const FusedLayer &jb, uint32_t it, const LimbConsts &lc, uint32_t *ctr,
                                  uint32_t *err) {
@@ -254,7 +264,7 @@ __device__ __forceinline__ void fz_mac_conv_item(const FusedLayer &jb, uint32_t 
     }
     // the last MAC item of (b, l) returns the NTT counters it waited on to zero
     const uint32_t per_bl = chunks * ngroups;
-    if (fz_signal_last(ctr + (jb.B * L * 4u + b * L + l) * jb.ctr_stride, per_bl) && threadIdx.x < 4)
+    if (fz_signal_last(ctr + (jb.n_tiles * L * 4u + b * L + l) * jb.ctr_stride, per_bl) && threadIdx.x < 4)
         st_dev(ctr + ((b * L + l) * 4u + threadIdx.x) * jb.ctr_stride, 0u);
 }
 
@@ -337,7 +347,7 @@ __device__ __forceinline__ void fz_mac_wide_item(const FusedLayer &jb, uint32_t 
         if (r + 1 < rounds) load_round(r + 1);
     }
     // the count only: the NTT counters of (b, l) are returned to zero by its last tail item
-    fz_signal(ctr + (jb.B * L * 4u + b * L + l) * jb.ctr_stride, 1u);
+    fz_signal(ctr + (jb.n_tiles * L * 4u + b * L + l) * jb.ctr_stride, 1u);
 }
 
 __device__ __forceinline__ void fz_mac_wide_switch(const FusedLayer &jb, uint32_t it, const LimbConsts &lc,
@@ -347,6 +357,40 @@ __device__ __forceinline__ void fz_mac_wide_switch(const FusedLayer &jb, uint32_
         case 2: fz_mac_wide_item<2>(jb, it, lc, ctr, err); break;
         case 4: fz_mac_wide_item<4>(jb, it, lc, ctr, err); break;
         default: fz_mac_wide_item<8>(jb, it, lc, ctr, err); break;
+    }
+}
+
+// ------------------------------------------------------------------ MAC items, image tiles (conv)
+// Grouped launch at larger batches: one LDS-staged tile of the batched MAC (images x channels of
+// one limb over a range of slots, mac_device.h) per item, so that a resident operand word is read
+// once per tile of images instead of once per image.  It waits for the NTT sub-block holding its
+// slot range for every image of its tile (one counter per tile), stores its block sums with
+// device scope and counts itself done for the tile.
+template <int GS>
+__device__ __forceinline__ void fz_mac_tile_item(const FusedLayer &jb, uint32_t it, uint32_t *lds,
+                                                 const LimbConsts &lc, uint32_t *ctr, uint32_t *err) {
+    const MacLdsGeom &gm = jb.gm;
+    const uint32_t L = jb.L;
+    uint32_t w = it;
+    const uint32_t bt = w % gm.tiles_b;
+    w /= gm.tiles_b;
+    w /= gm.tiles_n;
+    const uint32_t range = w % gm.ranges;
+    const uint32_t l = w / gm.ranges;
+    const uint32_t sub = (range * gm.R * gm.cpb) >> (jb.logN - 2);
+    fz_wait(ctr + ((bt * L + l) * 4u + sub) * jb.ctr_stride, fz_tile_imgs(jb, bt) * (jb.ntt_c0 + jb.ntt_sh), err);
+    mac_lds_tile<GS, true>(jb.x, jb.op, jb.h, jb.B, jb.Jtot, jb.Juse, jb.rows, L, 1u << jb.logN, jb.s_log, gm, it,
+                           lds, lc);
+    fz_signal(ctr + (jb.n_tiles * L * 4u + bt * L + l) * jb.ctr_stride, 1u);
+}
+
+__device__ __forceinline__ void fz_mac_tile_switch(const FusedLayer &jb, uint32_t it, uint32_t *lds,
+                                                   const LimbConsts &lc, uint32_t *ctr, uint32_t *err) {
+    switch (jb.gm.GS) {
+        case 2: fz_mac_tile_item<2>(jb, it, lds, lc, ctr, err); break;
+        case 4: fz_mac_tile_item<4>(jb, it, lds, lc, ctr, err); break;
+        case 8: fz_mac_tile_item<8>(jb, it, lds, lc, ctr, err); break;
+        default: fz_mac_tile_item<16>(jb, it, lds, lc, ctr, err); break;
     }
 }
 
@@ -398,7 +442,8 @@ __device__ __forceinline__ void fz_tail_item(const FusedLayer &jb, uint32_t it, 
         const uint32_t e = tid + i * FZ_THREADS;
         shv[i] = (sh && e < total) ? sh[((e >> span_log) << s_log) + c_lo + (e & ((1u << span_log) - 1u))] : 0u;
     }
-    fz_wait(ctr + (jb.B * L * 4u + b * L + l) * jb.ctr_stride, jb.mac_per_bl, err);
+    const uint32_t bt = b >> jb.tile_log;
+    fz_wait(ctr + (jb.n_tiles * L * 4u + bt * L + l) * jb.ctr_stride, jb.mac_per_bl, err);
     if (active) {
         const uint32_t *src = jb.h + ((size_t)(b * c_o + (exists ? n : 0)) * L + l) * M;
 #pragma unroll
@@ -435,15 +480,16 @@ __device__ __forceinline__ void fz_tail_item(const FusedLayer &jb, uint32_t it, 
         const uint32_t m = e >> span_log, off = e & ((1u << span_log) - 1u);
         put(e, sh ? sh[(m << s_log) + c_lo + off] : 0u);
     }
-    // the last tail item of (b, l) returns its counters to zero (every tail of (b, l) has waited)
-    uint32_t *mac_done = ctr + (jb.B * L * 4u + b * L + l) * jb.ctr_stride;
-    uint32_t *tail_done = ctr + (jb.B * L * 5u + b * L + l) * jb.ctr_stride;
-    if (fz_signal_last(tail_done, K_out * chunks)) {
+    // the last tail item of the tile and limb returns its counters to zero (every tail of them has
+    // waited); the NTT counters too, unless the MAC items do that (ng > 0)
+    uint32_t *mac_done = ctr + (jb.n_tiles * L * 4u + bt * L + l) * jb.ctr_stride;
+    uint32_t *tail_done = ctr + (jb.n_tiles * L * 5u + bt * L + l) * jb.ctr_stride;
+    if (fz_signal_last(tail_done, K_out * chunks * fz_tile_imgs(jb, bt))) {
         if (threadIdx.x == 0) {
             st_dev(mac_done, 0u);
             st_dev(tail_done, 0u);
         }
-        if (jb.ng == 0 && threadIdx.x < 4) st_dev(ctr + ((b * L + l) * 4u + threadIdx.x) * jb.ctr_stride, 0u);
+        if (jb.ng == 0 && threadIdx.x < 4) st_dev(ctr + ((bt * L + l) * 4u + threadIdx.x) * jb.ctr_stride, 0u);
     }
 }
 
@@ -545,8 +591,8 @@ __device__ __forceinline__ void fz_fc_item(const FusedLayer &jb, uint32_t it, ui
     }
     // the last item of (b, l) over every block returns the NTT counters of (b, l) to zero; the
     // last of this (b, blk, l)'s items finishes the block and returns its own counter to zero
-    uint32_t *bl_done = ctr + (jb.B * L * 4u + b * L + l) * jb.ctr_stride;
-    uint32_t *blk_done = ctr + (jb.B * L * 5u + (b * jb.rows + blk) * L + l) * jb.ctr_stride;
+    uint32_t *bl_done = ctr + (jb.n_tiles * L * 4u + b * L + l) * jb.ctr_stride;
+    uint32_t *blk_done = ctr + (jb.n_tiles * L * 5u + (b * jb.rows + blk) * L + l) * jb.ctr_stride;
     bool last_bl, last_blk;
     fz_signal_last2(bl_done, jb.rows * chunks * mgroups, blk_done, chunks * mgroups, &last_bl, &last_blk);
     if (last_bl) {
@@ -814,6 +860,74 @@ k_fused_layer(FusedLayer jb, const uint32_t *__restrict__ tw, const uint32_t *__
     }
 }
 
+// ------------------------------------------------------------------ the grouped launch
+// The items of every job, phase by phase: all NTT items, then all MAC items, then all tail
+// items, so that an item waits only for items of earlier phases, which have lower workgroup ids
+// (the argument at the top of the file).  Phase p takes 8 per_p workgroups from a multiple of 8;
+// within a phase the ids are remapped as by xcd_logical, so that neighbouring items of one job
+// (the sub-blocks of one row, the slot ranges of one tile) share an XCD and its L2; workgroups
+// past the phase's item count return at once.  The job of an item is found by a binary search
+// over the jobs' first items of that phase.
+// Three workgroups per CU (at most 168 VGPRs, what the tiled MAC item takes alone): the MAC and
+// inverse items of batched calls need the occupancy, so the NTT items keep fewer twiddles in
+// registers than in the one-layer launch, and a per-image MAC takes the channel-group item (the
+// all-channel item holds too many operand words in registers).
+constexpr int FG_LDS = 6656;   // words: the largest tiled MAC stage pair (2 x 24 rows x 34 words) and more
+constexpr int FG_TWB = 1024;
+static_assert(FG_LDS >= FZ_LDS, "the group's LDS holds every item's");
+
+__global__ void __launch_bounds__(FZ_THREADS, 3)
+k_fused_group(const FusedJob *__restrict__ jobs, uint32_t n_jobs, uint32_t c0, uint32_t c1, uint32_t c2,
+              uint32_t *__restrict__ sync) {
+    __shared__ __align__(16) uint32_t lds[FG_LDS];   // 16-byte aligned: the tiled MAC reads 8-byte pairs
+    const uint32_t p0 = (c0 + 7u) >> 3, p1 = (c1 + 7u) >> 3, p2 = (c2 + 7u) >> 3;
+    uint32_t t = blockIdx.x, phase, count, per;
+    if (t < 8u * p0) {
+        phase = 0;
+        count = c0;
+        per = p0;
+    } else if ((t -= 8u * p0) < 8u * p1) {
+        phase = 1;
+        count = c1;
+        per = p1;
+    } else {
+        t -= 8u * p1;
+        phase = 2;
+        count = c2;
+        per = p2;
+    }
+    const uint32_t item = (t & 7u) * per + (t >> 3);
+    if (item >= count) return;
+    uint32_t lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].first[phase] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const FusedJob &J = jobs[lo];
+    const FusedLayer &jb = J.jb;
+    const LimbConsts &lc = *J.lc;
+    const uint32_t it = item - J.first[phase];
+    uint32_t *err = sync + FZ_SB_ERR;
+    uint32_t *ctr = sync + FZ_SB_HDR + J.ctr_off;
+    if (phase == 0) {
+        switch (jb.logN) {
+            case 12: fz_ntt_item<12, FG_TWB>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
+            case 13: fz_ntt_item<13, FG_TWB>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
+            default: fz_ntt_item<14, FG_TWB>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
+        }
+    } else if (phase == 1) {
+        if (jb.kind != FZ_KIND_CONV)
+            fz_fc_item(jb, it, lds, J.xinv, lc, ctr, err);
+        else if (jb.mac_tiled)
+            fz_mac_tile_switch(jb, it, lds, lc, ctr, err);
+        else
+            fz_mac_conv_item(jb, it, lc, ctr, err);   // no_wide: the plan gave ng >= 1
+    } else {
+        fz_tail_switch(jb, it, lds, J.twi, J.twish, lc, ctr, err);
+    }
+}
+
 }  // namespace
 
 bool fused_layer_ok(const FusedLayer &jb) {
@@ -840,6 +954,8 @@ bool fused_layer_ok(const FusedLayer &jb) {
 uint32_t fused_layer_plan(FusedLayer &jb) {
     const uint32_t N = 1u << jb.logN;
     const uint32_t chunks = N / FZ_CHUNK;
+    jb.tile_log = 0;
+    jb.n_tiles = jb.B;
     if (jb.rows_form) {
         // whole-row NTT items, then one item per output row (b, g, n', l)
         jb.n_ntt = jb.B * (jb.ntt_c0 + jb.ntt_sh) * jb.L;
@@ -854,10 +970,18 @@ uint32_t fused_layer_plan(FusedLayer &jb) {
     }
     jb.n_ntt = jb.B * (jb.ntt_c0 + jb.ntt_sh) * jb.L * 4u;
     if (jb.kind == FZ_KIND_CONV) {
-        if ((jb.Juse == 1 || jb.Juse == 2 || jb.Juse == 4 || jb.Juse == 8) && jb.s_log <= 7) {
+        if (jb.mac_tiled) {
+            // LDS-staged tiles of 4 TBq images (one counter tile each) x 4 TNq channels
+            jb.ng = 0;
+            jb.tile_log = 31u - __builtin_clz(4u * jb.gm.TBq);
+            jb.n_tiles = jb.gm.tiles_b;
+            jb.mac_per_bl = jb.gm.ranges * jb.gm.tiles_n;
+            jb.n_mac = jb.L * jb.gm.ranges * jb.gm.tiles_b * jb.gm.tiles_n;
+        } else if (!jb.no_wide && (jb.Juse == 1 || jb.Juse == 2 || jb.Juse == 4 || jb.Juse == 8) && jb.s_log <= 7) {
             // every channel of a 128-slot chunk per item (ng = 0 marks this form)
             jb.ng = 0;
             jb.mac_per_bl = N / FZ_WCHUNK;
+            jb.n_mac = jb.B * jb.L * jb.mac_per_bl;
         } else {
             // channels per MAC item: about a thousand items, up to 4 channels each
             const uint64_t base = (uint64_t)jb.B * jb.L * chunks * jb.rows;
@@ -865,8 +989,8 @@ uint32_t fused_layer_plan(FusedLayer &jb) {
             while (ng < 4 && base / (2 * ng) >= 1024) ng <<= 1;
             jb.ng = ng;
             jb.mac_per_bl = chunks * ((jb.rows + ng - 1) / ng);
+            jb.n_mac = jb.B * jb.L * jb.mac_per_bl;
         }
-        jb.n_mac = jb.B * jb.L * jb.mac_per_bl;
         const uint32_t logm = jb.logN - jb.s_log;
         const uint32_t logr = logm > 10 ? logm - 8 : 2;
         const uint32_t T = 1u << (logm - logr);
@@ -874,7 +998,7 @@ uint32_t fused_layer_plan(FusedLayer &jb) {
         if (rw > jb.g_o) rw = jb.g_o;
         jb.tail_rw = rw;
         jb.n_inv = jb.B * jb.K_out * jb.L * (jb.g_o / rw);
-        jb.n_ctr = jb.B * jb.L * 4u + 2u * jb.B * jb.L;       // NTT sub-blocks, MAC done, tails done
+        jb.n_ctr = jb.n_tiles * jb.L * 6u;       // per tile and limb: NTT sub-blocks (4), MAC done, tails done
     } else {
         const uint32_t mr = jb.n_o_p < (uint32_t)FZ_MR ? jb.n_o_p : (uint32_t)FZ_MR;
         jb.ng = 1;
@@ -924,5 +1048,17 @@ hipError_t launch_fused_layer(const FusedLayer &jb, const uint32_t *tw, const ui
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+uint32_t fused_group_lds_bytes() { return (uint32_t)FG_LDS * 4u; }
+
+hipError_t launch_fused_group(const FusedJob *jobs, uint32_t n_jobs, const uint32_t count[3], uint32_t *sync,
+                              hipStream_t st, const LaunchEv *ev) {
+    if (n_jobs == 0) return hipSuccess;
+    const uint32_t grid = xcd_grid(count[0]) + xcd_grid(count[1]) + xcd_grid(count[2]);
+    if (grid == 0) return hipSuccess;
+    HE_LAUNCH(ev, k_fused_group, dim3(grid), dim3(FZ_THREADS), 0, st, jobs, n_jobs, count[0], count[1], count[2],
+              sync);
     return hipGetLastError();
 }

@@ -15,6 +15,7 @@
 // wave shuffles), leaving N/s values per channel for an (N/s)-point tail.
 
 #include "he_kernels.h"
+#include "mac_device.h"
 
 namespace {
 
@@ -182,166 +183,18 @@ k_mac_tiled(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uin
 }
 
 // ------------------------------------------------------------------ batched MAC, LDS-staged
-// Residue-class form only.  Per NTT slot the MAC is a small product of an
-// (images x J) and a (J x channels) matrix, summed over the s slots of each
-// block.  A workgroup takes a tile of TB images x TN channels of one limb and a
-// range of slots; per stage (one input row J, R slots) it stages the TB + TN
-// rows of R words in LDS (double-buffered, loads of the next stage in flight
-// during the products), and each thread accumulates a 4 x 4 sub-tile (images
-// bi + TBq u, channels ni + TNq v) over GS consecutive slots of one block, so a
-// staged word feeds 4 products from LDS and a global word TB or TN.  Threads are
-// split into G groups by slot span; when a block spans several groups their
-// sums are added through LDS at the end.  The 64-bit sums are kept below 2^64 by
-// replacing hi 2^32 + lo with hi (2^32 mod q) + lo (one multiply-add) every 10
-// products, and reduced mod q once at the end.
-constexpr int ML_THREADS = 256;
-constexpr int ML_UNITS = 4;          // 16-byte staging loads per thread and stage (R <= 32)
-constexpr int ML_RED_STRIDE = 17;    // words per thread in the cross-group sum (16 + pad)
-
+// (mac_device.h holds the tile body.)
 template <int GS>
 __global__ void __launch_bounds__(ML_THREADS)
 k_mac_lds(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ h, uint32_t B,
           uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s_log, MacLdsGeom gm,
           uint32_t xcd_order, LimbConsts lc) {
     extern __shared__ uint32_t lds[];
-    // rows padded by two words: 8-byte aligned pairs, and 16 rows of a wave on distinct banks
-    const uint32_t TBq = gm.TBq, TNq = gm.TNq, TB = 4 * TBq, TN = 4 * TNq, RP = gm.R + 2, R4 = gm.R >> 2;
-    const uint32_t buf_words = (TB + TN) * RP;   // one stage: one input row J, R slots
     // xcd_order: consecutive tiles and slot ranges on one XCD (see xcd_logical); otherwise the
     // round-robin dealing of workgroup ids spreads them over the XCDs
     uint32_t w = blockIdx.x;
     if (xcd_order && !xcd_logical(blockIdx.x, L * gm.ranges * gm.tiles_b * gm.tiles_n, w)) return;
-    const uint32_t tb = w % gm.tiles_b;
-    w /= gm.tiles_b;
-    const uint32_t tn = w % gm.tiles_n;
-    w /= gm.tiles_n;
-    const uint32_t range = w % gm.ranges;
-    const uint32_t l = w / gm.ranges;
-    const uint32_t b0 = tb * TB, n0 = tn * TN;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t sub = tid % (TBq * TNq);
-    const uint32_t g = tid / (TBq * TNq);
-    const uint32_t bi = sub / TNq, ni = sub % TNq;
-    const LimbConst c = lc.l[l];
-    const uint32_t base = range * gm.R * gm.cpb;
-    const uint32_t stages = Juse * gm.cpb;
-    const uint32_t units = (TB + TN) * R4;
-
-    // staging unit u of stage st: input row J = st / cpb, row u / R4 of the tile (x rows first,
-    // then operand rows), 4 words at column 4 (u % R4)
-    auto load_stage = [&](uint32_t st, uint4 (&pre)[ML_UNITS]) {
-        const uint32_t J = st / gm.cpb, k_st = base + (st % gm.cpb) * gm.R;
-#pragma unroll
-        for (int i = 0; i < ML_UNITS; ++i) {
-            const uint32_t u = tid + i * ML_THREADS;
-            if (u < units) {
-                const uint32_t row = u / R4, k = k_st + (u % R4) * 4;
-                const uint32_t *src;
-                if (row < TB) {
-                    const uint32_t b = min(b0 + row, B - 1);
-                    src = X + (((size_t)b * Jtot + J) * L + l) * N + k;
-                } else {
-                    const uint32_t n = min(n0 + row - TB, c_o - 1);
-                    src = Op + (((size_t)n * L + l) * Jtot + J) * N + k;
-                }
-                pre[i] = *reinterpret_cast<const uint4 *>(src);
-            }
-        }
-    };
-    auto store_stage = [&](uint32_t buf, const uint4 (&pre)[ML_UNITS]) {
-        uint32_t *dst = lds + buf * buf_words;
-#pragma unroll
-        for (int i = 0; i < ML_UNITS; ++i) {
-            const uint32_t u = tid + i * ML_THREADS;
-            if (u < units) {
-                uint2 *d = reinterpret_cast<uint2 *>(dst + (u / R4) * RP + (u % R4) * 4);
-                d[0] = make_uint2(pre[i].x, pre[i].y);
-                d[1] = make_uint2(pre[i].z, pre[i].w);
-            }
-        }
-    };
-
-    uint64_t acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
-    uint32_t pc = 0;   // products in acc since the last fold (uniform)
-    uint4 pre[ML_UNITS];
-    load_stage(0, pre);
-    store_stage(0, pre);
-    __syncthreads();
-    const uint32_t off = g * GS;   // even: 8-byte aligned pairs
-    for (uint32_t st = 0; st < stages; ++st) {
-        const uint32_t buf = st & 1u;
-        if (st + 1 < stages) load_stage(st + 1, pre);
-        const uint32_t *xs = lds + buf * buf_words + off;
-        const uint32_t *os = xs + TB * RP;
-        const uint2 *xr[4], *orow[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            xr[u] = reinterpret_cast<const uint2 *>(xs + (bi + TBq * u) * RP);
-            orow[u] = reinterpret_cast<const uint2 *>(os + (ni + TNq * u) * RP);
-        }
-#pragma unroll
-        for (int k2 = 0; k2 < GS / 2; ++k2) {   // two slots per 8-byte read
-            uint2 xv[4], ov[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                xv[u] = xr[u][k2];
-                ov[u] = orow[u][k2];
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j] += (uint64_t)xv[i].x * ov[j].x;
-                    acc[i][j] += (uint64_t)xv[i].y * ov[j].y;
-                }
-            pc += 2;
-            if (pc >= 10) {
-                // hi 2^32 + lo == hi (2^32 mod q) + lo: below 2^62 + 2^32, and ten more
-                // products keep the sum below 2^64
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = (uint64_t)(uint32_t)(acc[i][j] >> 32) * c.r32 + (acc[i][j] & 0xffffffffull);
-                pc = 0;
-            }
-        }
-        if (st + 1 < stages) store_stage(buf ^ 1u, pre);
-        __syncthreads();
-    }
-    uint32_t v[16];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[i * 4 + j] = reduce64(acc[i][j], c);
-    if (gm.gpb > 1) {
-        // the gpb groups that share a block are consecutive; the first adds the others' sums
-        uint32_t *red = lds;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) red[tid * ML_RED_STRIDE + u] = v[u];
-        __syncthreads();
-        if (g % gm.gpb == 0) {
-            for (uint32_t p = 1; p < gm.gpb; ++p) {
-                const uint32_t *o = red + (tid + p * TBq * TNq) * ML_RED_STRIDE;
-#pragma unroll
-                for (int u = 0; u < 16; ++u) v[u] = addmod(v[u], o[u], c.q);
-            }
-        }
-    }
-    if (g % gm.gpb != 0) return;
-    const uint32_t M = N >> s_log;
-    const uint32_t m = (base + off) >> s_log;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t b = b0 + bi + TBq * i, n = n0 + ni + TNq * j;
-            if (b < B && n < c_o) h[((size_t)(b * c_o + n) * L + l) * M + m] = v[i * 4 + j];
-        }
+    mac_lds_tile<GS, false>(X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, w, lds, lc);
 }
 
 // ------------------------------------------------------------------ batched MAC, staged by LDS DMA

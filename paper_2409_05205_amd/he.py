@@ -35,11 +35,15 @@ EXPORTED = [
     "he_layer_inputs_ntt", "he_conv_layer_ntt", "he_fc_layer_ntt",
     "he_pack_operands", "he_client_masks", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
     "he_layer_geometry", "he_ctx_workspace_bytes", "he_workspace_reserve", "he_conv_layer_noalloc",
-    "he_sync_check",
+    "he_sync_check", "he_probe_rate",
+    "he_group_create", "he_group_run", "he_group_check", "he_group_items", "he_group_free",
 ]
+HE_PROBE_BFLY, HE_PROBE_GSBFLY, HE_PROBE_MAD64, HE_PROBE_ADD, HE_PROBE_MULLO, HE_PROBE_MULHI = 1, 2, 3, 4, 5, 6
 NOALLOC_SCRATCH_BYTES = 32 << 20   # HE_NOALLOC_SCRATCH_BYTES in include/he.h
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
-HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL, HE_K_LAYER = 1, 2, 4, 8, 16, 32
+HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL, HE_K_LAYER, HE_K_LAYER_ROWS = 1, 2, 4, 8, 16, 32, 64
+HE_K_GROUP = 128
+HE_GROUP_MAC_AUTO, HE_GROUP_MAC_PER_IMAGE, HE_GROUP_MAC_TILED = 0, 1, 2
 
 
 class HEError(RuntimeError):
@@ -58,6 +62,12 @@ class LayerDesc(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("timeout_s", ctypes.c_double)]
+
+
+class LayerCall(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("layer", ctypes.c_void_p), ("B", ctypes.c_uint32),
+                ("d_c0", ctypes.c_void_p), ("d_sh", ctypes.c_void_p), ("d_sh_next", ctypes.c_void_p),
+                ("d_out", ctypes.c_void_p)]
 
 
 class LayerInfo(ctypes.Structure):
@@ -98,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
     lib.he_conv_layer_noalloc.argtypes = [VP, VP, U32, VP, VP, VP, VP, VP]
     lib.he_sync_check.argtypes = [VP, VP]
+    lib.he_probe_rate.argtypes = [U32, U32, P(ctypes.c_double), P(ctypes.c_double)]
     for name in ("he_conv_layer_ws", "he_fc_layer_ws"):
         getattr(lib, name).argtypes = [VP, VP, U32, VP, VP, VP, VP, VP, SZ, VP]
     lib.he_layer_inputs_ntt.argtypes = [VP, VP, U32, VP, VP, VP, VP]
@@ -134,6 +145,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_tune_force.argtypes = [VP, U32, ctypes.c_int32]
     lib.he_autotune_layer.argtypes = [VP, VP, U32, VP]
     lib.he_tune_get.argtypes = [VP, U32, U32, U32, P(ctypes.c_int32)]
+    lib.he_group_create.argtypes = [P(LayerCall), U32, U32, P(VP)]
+    lib.he_group_run.argtypes = [VP, VP]
+    lib.he_group_check.argtypes = [VP, VP]
+    lib.he_group_items.argtypes = [VP, P(U32), P(U32), P(SZ)]
+    lib.he_group_free.argtypes = [VP]
     lib.he_free_layer.argtypes = [VP]
     lib.he_free.argtypes = [VP]
     lib.he_strerror.argtypes = [ctypes.c_int]
@@ -141,7 +157,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name not in ("he_layer_workspace_bytes", "he_strerror", "he_last_error", "he_free", "he_free_layer",
-                        "he_seq_length", "he_seq_free", "he_server_requests", "he_server_free",
+                        "he_seq_length", "he_seq_free", "he_server_requests", "he_server_free", "he_group_free",
                         "he_ctx_workspace_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -535,6 +551,13 @@ class Context:
             pass
 
 
+def probe_rate(kind: int, iters: int = 4096):
+    """he_probe_rate: (operations per second of the whole chip, ms of the timed launch)."""
+    ops, ms = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().he_probe_rate(kind, iters, ctypes.byref(ops), ctypes.byref(ms)), "he_probe_rate")
+    return ops.value, ms.value
+
+
 class Sequence:
     """A recorded list of layer calls (he_seq_*): eager run, or hipGraph capture and replay.
 
@@ -585,6 +608,79 @@ class Sequence:
     def free(self):
         if getattr(self, "handle", None):
             load_library().he_seq_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+
+class Group:
+    """Independent layer calls evaluated by one grouped launch (he_group_*).
+
+    add() the calls (any layers of any contexts on one device), then build() once; run() is one
+    launch.  Keeps references to the layers and buffers so they outlive it.
+    """
+
+    def __init__(self):
+        self.handle = None
+        self._calls = []
+        self._keep = []
+
+    def add(self, layer: Layer, c0, sh=None, sh_next=None, out=None):
+        import torch
+        if self.handle is not None:
+            raise RuntimeError("Group: add after build")
+        ctx = layer.ctx
+        B = c0.shape[0]
+        i = layer.info
+        if layer.kind == HE_LAYER_CONV:
+            _check_dev(c0, (B, i.K_in, ctx.L, ctx.N), "c0")
+            _check_dev(sh, (B, i.K_in, ctx.N), "sh", True)
+            _check_dev(sh_next, (B, i.K_out, ctx.N), "sh_next", True)
+            shape = (B, i.K_out, ctx.L, ctx.N)
+        else:
+            _check_dev(c0, (B, ctx.L, ctx.N), "c0")
+            _check_dev(sh, (B, ctx.N), "sh", True)
+            _check_dev(sh_next, (B, i.blocks, i.n_o_p), "sh_next", True)
+            shape = (B, i.blocks, ctx.L, i.n_o_p)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.int32, device=c0.device)
+        _check_dev(out, shape, "out")
+        self._calls.append(LayerCall(ctx.handle, layer.handle, B, _ptr(c0), _ptr(sh), _ptr(sh_next), _ptr(out)))
+        self._keep.append((ctx, layer, c0, sh, sh_next, out))
+        return out
+
+    def build(self, flags: int = HE_GROUP_MAC_AUTO):
+        arr = (LayerCall * len(self._calls))(*self._calls)
+        h = ctypes.c_void_p()
+        _check(load_library().he_group_create(arr, len(self._calls), flags, ctypes.byref(h)), "he_group_create")
+        self.handle = h
+        return self
+
+    def run(self, stream=None):
+        _check(load_library().he_group_run(self.handle, _stream(stream)), "he_group_run")
+
+    def check(self, stream=None):
+        _check(load_library().he_group_check(self.handle, _stream(stream)), "he_group_check")
+
+    def items(self):
+        """(work items per phase (NTT, MAC, inverse), calls with image-tiled MAC, workspace bytes)."""
+        it = (ctypes.c_uint32 * 3)()
+        tiled, ws = ctypes.c_uint32(), ctypes.c_size_t()
+        _check(load_library().he_group_items(self.handle, it, ctypes.byref(tiled), ctypes.byref(ws)),
+               "he_group_items")
+        return tuple(int(x) for x in it), int(tiled.value), int(ws.value)
+
+    def __len__(self):
+        return len(self._calls)
+
+    def free(self):
+        if getattr(self, "handle", None):
+            load_library().he_group_free(self.handle)
             self.handle = None
 
     def __del__(self):

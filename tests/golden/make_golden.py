@@ -9,7 +9,7 @@ evaluation, decryption) and asserts that every decrypted output minus the fresh
 share equals the integer layer output mod t, i.e. that the closed loop of the
 harness holds.  Nothing here touches the GPU library.
 
-Usage: python tests/golden/make_golden.py
+Usage: python tests/golden/make_golden.py [--only NAME ...]
 """
 from __future__ import annotations
 
@@ -82,9 +82,7 @@ def run_stack(name, cfg, width, classes, N, L, idx, decrypt):
     return res
 
 
-def main():
-    out = {"note": "SHA-256 of the oracle's c0^r (little-endian u32) per layer; written by make_golden.py",
-           "cases": {}}
+def case_single_conv():
     # single conv workload: conv 3->16 on 3x32x32, N=4096, L=3, first layer with a fresh share
     ctx = bfv.make_ctx(4096, 3, wl.T_PLAIN)
     _, b = cases.client_key(ctx, wl.CONFIG_SINGLE_CONV, 0)
@@ -94,41 +92,73 @@ def main():
     o = bfv.server_conv(ctx, inp["geom"], inp["c0"], inp["rho"], inp["fhat"], inp["sh"], inp["sh_next"])
     F = wl.layer_weights(wl.CONFIG_SINGLE_CONV, 0, 0, shp)
     check_conv_decrypt(ctx, wl.CONFIG_SINGLE_CONV, 0, 0, inp, o, network.conv2d(x, F), b)
-    out["cases"]["single_conv"] = {"config": 1, "N": 4096, "L": 3,
-                                   "layers": {"0": {"kind": "conv", "digest": cases.digest(o),
-                                                    "shape": list(o.shape)}}}
-    name, cfg, width, classes, N, L, idx = cases.PLAIN20_X1
-    out["cases"][name] = run_stack(name, cfg, width, classes, N, L, idx, decrypt=True)
-    for name, cfg, width, classes, N, L, idx in cases.WIDE_SAMPLES:
-        out["cases"][name] = run_stack(name, cfg, width, classes, N, L, idx, decrypt=False)
-    for name, cfg, width, classes, N, L, k, B, images in cases.BATCHED_SAMPLES:
-        ctx = bfv.make_ctx(N, L, wl.T_PLAIN)
-        inp = cases.batched_layer_inputs(cfg, width, classes, k, B, N, ctx.primes)
-        g = inp["geom"]
-        fh = packing.pack_conv_filters(inp["F"], g)
-        res = {"config": cfg, "width": width, "classes": classes, "N": N, "L": L, "layer": k, "batch": B,
-               "images": {}}
-        for b in images:
-            t0 = time.time()
-            o = bfv.server_conv(ctx, g, inp["c0"][b].astype(np.uint64), inp["rho"], fh, inp["sh"][b],
-                                inp["sh_next"][b])
-            res["images"][str(b)] = cases.digest(o)
-            print(f"{name} image {b} {time.time() - t0:.1f}s", flush=True)
-        out["cases"][name] = res
-    ctx = bfv.make_ctx(16384, 6, wl.T_PLAIN)
-    for name, k in cases.RESNET_SAMPLES:
+    return {"config": 1, "N": 4096, "L": 3,
+            "layers": {"0": {"kind": "conv", "digest": cases.digest(o), "shape": list(o.shape)}}}
+
+
+def case_batched(name, cfg, width, classes, N, L, k, B, images):
+    ctx = bfv.make_ctx(N, L, wl.T_PLAIN)
+    inp = cases.batched_layer_inputs(cfg, width, classes, k, B, N, ctx.primes)
+    g = inp["geom"]
+    fh = packing.pack_conv_filters(inp["F"], g)
+    res = {"config": cfg, "width": width, "classes": classes, "N": N, "L": L, "layer": k, "batch": B,
+           "images": {}}
+    for b in images:
         t0 = time.time()
-        inp = cases.resnet_layer_inputs(k, 16384, ctx.primes)
-        g = inp["geom"]
-        o = bfv.server_conv(ctx, g, inp["c0"].astype(np.uint64), inp["rho"], packing.pack_conv_filters(inp["F"], g),
-                            inp["sh"], inp["sh_next"])
-        out["cases"][name] = {"config": wl.CONFIG_RESNET50, "N": 16384, "L": 6, "layer": k,
-                              "layers": {str(k): {"kind": "conv", "digest": cases.digest(o), "shape": list(o.shape)}}}
-        print(f"{name} {inp['shape']} {time.time() - t0:.1f}s", flush=True)
-    with open(os.path.join(HERE, "server_digests.json"), "w") as f:
+        o = bfv.server_conv(ctx, g, inp["c0"][b].astype(np.uint64), inp["rho"], fh, inp["sh"][b],
+                            inp["sh_next"][b])
+        res["images"][str(b)] = cases.digest(o)
+        print(f"{name} image {b} {time.time() - t0:.1f}s", flush=True)
+    return res
+
+
+def case_resnet(name, k):
+    ctx = bfv.make_ctx(16384, 6, wl.T_PLAIN)
+    t0 = time.time()
+    inp = cases.resnet_layer_inputs(k, 16384, ctx.primes)
+    g = inp["geom"]
+    o = bfv.server_conv(ctx, g, inp["c0"].astype(np.uint64), inp["rho"], packing.pack_conv_filters(inp["F"], g),
+                        inp["sh"], inp["sh_next"])
+    print(f"{name} {inp['shape']} {time.time() - t0:.1f}s", flush=True)
+    return {"config": wl.CONFIG_RESNET50, "N": 16384, "L": 6, "layer": k,
+            "layers": {str(k): {"kind": "conv", "digest": cases.digest(o), "shape": list(o.shape)}}}
+
+
+def all_cases():
+    """name -> function computing the case's record."""
+    out = {"single_conv": case_single_conv}
+    name, cfg, width, classes, N, L, idx = cases.PLAIN20_X1
+    out[name] = lambda a=(name, cfg, width, classes, N, L, idx): run_stack(*a, decrypt=True)
+    for name, cfg, width, classes, N, L, idx in cases.WIDE_SAMPLES:
+        out[name] = lambda a=(name, cfg, width, classes, N, L, idx): run_stack(*a, decrypt=False)
+    for c in cases.BATCHED_SAMPLES:
+        out[c[0]] = lambda c=c: case_batched(*c)
+    for name, k in cases.RESNET_SAMPLES:
+        out[name] = lambda a=(name, k): case_resnet(*a)
+    return out
+
+
+def main(argv):
+    """Every case, or with --only NAME [NAME ...] just those, merged into the stored file."""
+    path = os.path.join(HERE, "server_digests.json")
+    table = all_cases()
+    if argv[:1] == ["--only"]:
+        names = argv[1:]
+        unknown = [n for n in names if n not in table]
+        if unknown:
+            raise SystemExit(f"unknown cases: {unknown}")
+        with open(path) as f:
+            out = json.load(f)
+    else:
+        names = list(table)
+        out = {"note": "SHA-256 of the oracle's c0^r (little-endian u32) per layer; written by make_golden.py",
+               "cases": {}}
+    for n in names:
+        out["cases"][n] = table[n]()
+    with open(path, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
     print("wrote server_digests.json")
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

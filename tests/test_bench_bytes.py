@@ -57,34 +57,53 @@ def test_mac_bytes_and_counts():
     assert st.tail_butterflies() == 64 * 16 * L * (M // 2) * 11 + 32 * 1 * L * (N // 2) * 13
 
 
-def _current(kind):
-    """The counter record with its hash set to the sources as they are now."""
+def _sha(files):
     import hashlib
     import os
-    rec = dict(bench.PMC_TRAFFIC[kind])
     h = hashlib.sha256()
-    for src in rec["sources"]:
+    for src in files:
         with open(os.path.join(bench.ROOT, src), "rb") as f:
             h.update(f.read())
-    rec["sha256"] = h.hexdigest()
+    return h.hexdigest()
+
+
+def _current(kind):
+    """The counter record with the hash of every form set to the sources as they are now."""
+    rec = dict(bench.PMC_TRAFFIC[kind])
+    if "forms" in rec:
+        rec["forms"] = {c: dict(f, sha256=_sha(f["sources"])) for c, f in rec["forms"].items()}
+    else:
+        rec["sha256"] = _sha(rec["sources"])
     return rec
 
 
-def test_counter_traffic_follows_the_per_layer_mac_forms(monkeypatch):
-    monkeypatch.setitem(bench.PMC_TRAFFIC, "mac", _current("mac"))
-    table = bench.PMC_TRAFFIC["mac"]["per_layer"]
+def test_counter_traffic_follows_the_per_layer_forms(monkeypatch):
+    monkeypatch.setitem(bench.PMC_TRAFFIC, "layers", _current("layers"))
+    table = bench.PMC_TRAFFIC["layers"]["per_layer"]
     n = len(table)
     split = "S" * n
-    assert bench.pmc_traffic("mac", split) == round(sum(r["S"] for r in table) / n)
+    assert bench.pmc_traffic("layers", split) == round(sum(r["S"] for r in table) / n)
     mixed = "F" + "S" * (n - 2) + "S"
     want = (table[0]["F"] + sum(r["S"] for r in table[1:])) / n
-    assert bench.pmc_traffic("mac", mixed) == round(want)
+    assert bench.pmc_traffic("layers", mixed) == round(want)
+    # a selection: the one-launch layers of a plan apart from the multi-launch ones
+    plan = "O" + "S" * (n - 2) + "O"
+    one = [c == "O" for c in plan]
+    assert bench.pmc_traffic("layers", plan, one) == round((table[0]["O"] + table[-1]["O"]) / 2)
+    assert bench.pmc_traffic("layers", plan, [not o for o in one]) == round(
+        sum(r["S"] for r in table[1:-1]) / (n - 2))
     # the FC head has no fused form, a plan of the wrong length matches nothing
     assert table[-1]["F"] is None
-    assert bench.pmc_traffic("mac", "F" * n) is None
-    assert bench.pmc_traffic("mac", split[:-1]) is None
-    assert bench.pmc_traffic("mac") is None
-    # a kernel source changed since the counters were taken
-    stale = dict(bench.PMC_TRAFFIC["mac"], sha256="0" * 64)
-    monkeypatch.setitem(bench.PMC_TRAFFIC, "mac", stale)
-    assert bench.pmc_traffic("mac", split) is None
+    assert bench.pmc_traffic("layers", "F" * n) is None
+    assert bench.pmc_traffic("layers", split[:-1]) is None
+    assert bench.pmc_traffic("layers") is None
+    # a kernel source changed since the counters were taken: only that form's entries go
+    rec = _current("layers")
+    rec["forms"]["F"] = dict(rec["forms"]["F"], sha256="0" * 64)
+    monkeypatch.setitem(bench.PMC_TRAFFIC, "layers", rec)
+    assert bench.pmc_traffic("layers", split) is not None
+    assert bench.pmc_traffic("layers", mixed) is None
+    monkeypatch.setitem(bench.PMC_TRAFFIC, "ntt_fwd", dict(bench.PMC_TRAFFIC["ntt_fwd"], sha256="0" * 64))
+    assert bench.pmc_traffic("ntt_fwd") is None
+    monkeypatch.setitem(bench.PMC_TRAFFIC, "ntt_fwd", _current("ntt_fwd"))
+    assert bench.pmc_traffic("ntt_fwd") == bench.PMC_TRAFFIC["ntt_fwd"]["bytes_per_launch"]

@@ -33,10 +33,11 @@ def ctx4096(he):
 
 def _launches(ctx, he, fn):
     ctx.profile_reset()
-    ctx.profile_enable(he.HE_K_LAYER | he.HE_K_MAC | he.HE_K_MAC_TAIL | he.HE_K_NTT_FWD)
+    ctx.profile_enable(he.HE_K_LAYER | he.HE_K_LAYER_ROWS | he.HE_K_MAC | he.HE_K_MAC_TAIL | he.HE_K_NTT_FWD)
     out = fn()
     host(out)
-    n_layer = ctx.profile_read(he.HE_K_LAYER)[0]
+    # both one-launch forms (work items: HE_K_LAYER, rows: HE_K_LAYER_ROWS)
+    n_layer = ctx.profile_read(he.HE_K_LAYER)[0] + ctx.profile_read(he.HE_K_LAYER_ROWS)[0]
     n_other = sum(ctx.profile_read(k)[0] for k in (he.HE_K_MAC, he.HE_K_MAC_TAIL, he.HE_K_NTT_FWD))
     ctx.profile_enable(0)
     ctx.profile_reset()
