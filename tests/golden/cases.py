@@ -90,6 +90,7 @@ WIDE_SAMPLES = [
 # Batched full-size layers: (name, config, width, classes, N, L, layer, batch, sampled images).
 # The GPU runs the whole batch; the oracle digests of the sampled images are stored.
 BATCHED_SAMPLES = [
+    ("batched_x1_l7", wl.CONFIG_BATCHED, 1, 10, 8192, 4, 7, 64, [5, 60]),
     ("batched_x2_l1", wl.CONFIG_BATCHED, 2, 10, 8192, 4, 1, 64, [3, 62]),
     ("batched_x4_l1", wl.CONFIG_BATCHED, 4, 100, 16384, 6, 1, 64, [0, 45]),
 ]
@@ -109,9 +110,10 @@ def batched_layer_inputs(cfg, width, classes, k, B, N, primes):
     return {"shape": shp, "geom": g, "F": F, "rho": rho, "c0": c0, "sh": sh, "sh_next": shn}
 
 # ResNet-50-shaped layers at N = 16384, L = 6 (one image): (name, layer index in
-# workloads.resnet50_body()); a 3x3 at 28x28 (s = 16), a 1x1 expansion at 14x14 (s = 64)
-# and a 3x3 at 7x7 (s = 128).
-RESNET_SAMPLES = [("resnet50_l15", 15), ("resnet50_l29", 29), ("resnet50_l47", 47)]
+# workloads.resnet50_body()); the stride-2 1x1 projection of stage 2 packed on the subsampled
+# 28x28 map (256 -> 512), a 3x3 at 28x28 (s = 16), a 1x1 expansion at 14x14 (s = 64) and a 3x3
+# at 7x7 (s = 128).
+RESNET_SAMPLES = [("resnet50_l13", 13), ("resnet50_l15", 15), ("resnet50_l29", 29), ("resnet50_l47", 47)]
 
 
 def resnet_layer_inputs(k, N, primes):

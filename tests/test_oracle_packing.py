@@ -11,13 +11,17 @@
   exponent conventions.
 * FC packing is checked by brute force of Theorem 1, including the Fig. 5
   shape n_i = 4, n_o = 2 with N = n_i n_o.
+* The ResNet-50 stride-2 1x1 projections packed on the subsampled map: the
+  subsampled conv equals the strided one (brute force), and the HE layer on the
+  subsampled map decrypts to the strided conv of the full map.
 """
 import itertools
 
 import numpy as np
 import pytest
 
-from oracle import network, packing
+import workloads as wl
+from oracle import bfv, network, packing
 
 
 def int_negacyclic(a, b):
@@ -199,3 +203,60 @@ def test_workload_geometries():
     assert (f.n_o_p, f.n_i_p, f.blocks) == (16, 512, 1)
     f = packing.fc_geometry(16384, 256, 100)
     assert (f.n_o_p, f.n_i_p, f.blocks) == (64, 256, 2)
+
+
+# ------------------------------------------------------------------ ResNet-50 stride-2 projections
+def _loop_conv1x1(img, F, stride):
+    """Brute force: out[n][y][x] = sum_m F[n][m] img[m][stride y][stride x], no padding."""
+    c_o, c_i = F.shape[:2]
+    _, H, W = img.shape
+    Ho, Wo = (H - 1) // stride + 1, (W - 1) // stride + 1
+    out = np.zeros((c_o, Ho, Wo), dtype=np.int64)
+    for n in range(c_o):
+        for y in range(Ho):
+            for x in range(Wo):
+                out[n, y, x] = sum(int(F[n, m, 0, 0]) * int(img[m, stride * y, stride * x]) for m in range(c_i))
+    return out
+
+
+def test_resnet50_projections_are_subsampled_1x1():
+    """The stride-2 projections of the body are 1x1 stride-1 convs at the output size, fed by the
+    block input of the stage's first block; the strided form is still available."""
+    sub = wl.resnet50_body()
+    full = wl.resnet50_body(subsample_projections=False)
+    assert len(sub) == len(full) == 53
+    for k, (a, b) in enumerate(zip(sub, full)):
+        if k in wl.RESNET50_SUBSAMPLED_PROJECTIONS:
+            assert b.f == 1 and b.stride == 2 and b.pad == 0
+            assert (a.c_i, a.c_o, a.f, a.stride, a.pad) == (b.c_i, b.c_o, 1, 1, 0)
+            assert a.H == b.H // 2 and a.W == b.W // 2
+            # the output size of the strided conv is the subsampled map's
+            assert a.H == sub[k - 1].H               # the block's 1x1 expansion at the output size
+        else:
+            assert a == b
+    assert [k for k, s in enumerate(full) if s.kind == "conv" and s.f == 1 and s.stride == 2] == \
+        list(wl.RESNET50_SUBSAMPLED_PROJECTIONS)
+
+
+@pytest.mark.parametrize("c_i,c_o,H", [(3, 4, 8), (5, 2, 6), (4, 3, 7)])
+def test_subsampled_projection_equals_strided_conv(c_i, c_o, H):
+    """A 1x1 stride-2 conv equals the 1x1 conv of the even-pixel map (brute force; odd sizes too)."""
+    rng = np.random.default_rng(c_i * 100 + c_o * 10 + H)
+    img = rng.integers(0, 16, (c_i, H, H))
+    F = rng.integers(-7, 8, (c_o, c_i, 1, 1))
+    want = _loop_conv1x1(img, F, 2)
+    assert (network.conv2d(img, F, stride=2, pad=0) == want).all()
+    assert (network.conv2d(wl.projection_input(img), F, stride=1, pad=0) == want).all()
+
+
+def test_subsampled_projection_protocol_decrypts_to_strided_conv():
+    """The HE layer packed on the subsampled map decrypts (Alg. 1, oracle client and server) to
+    the integer stride-2 1x1 conv of the full map."""
+    ctx = bfv.make_ctx(256, 2, wl.T_PLAIN)
+    rng = np.random.default_rng(77)
+    c_i, c_o, H = 4, 6, 8
+    img = rng.integers(0, 16, (c_i, H, H))
+    F = rng.integers(-7, 8, (c_o, c_i, 1, 1))
+    shp = wl.ConvShape(c_i, c_o, H // 2, H // 2, f=1, stride=1, pad=0)
+    res = network.run_conv_protocol(ctx, shp, wl.projection_input(img), F, (99, 6, 0, c_i), False, False)
+    assert (network.centred(res["decrypted"], wl.T_PLAIN) == _loop_conv1x1(img, F, 2)).all()

@@ -123,12 +123,18 @@ def plain20(width: int = 1, classes: int = 10) -> List[object]:
     return L
 
 
-def resnet50_body(classes: int = 1000) -> List[object]:
+def resnet50_body(classes: int = 1000, subsample_projections: bool = True) -> List[object]:
     """The ResNet-50 linear layers after its stem, for a 224x224 input: bottleneck blocks
     (1x1 reduce, 3x3, 1x1 expand, and a 1x1 projection on the first block of a stage) at
     56x56 (3 blocks, 64/256 channels), 28x28 (4 blocks, 128/512), 14x14 (6 blocks, 256/1024)
     and 7x7 (3 blocks, 512/2048), the stride of a stage's first block on its 3x3 and its
     projection; then global average pooling and FC 2048 -> classes.  52 convs + 1 FC.
+
+    A 1x1 convolution of stride 2 reads only the pixels at even coordinates, so with
+    subsample_projections the stride-2 projections (layers 13, 26 and 45) are the same 1x1
+    convolution at stride 1 on the map subsampled to the output size (projection_input): each
+    party subsamples its share of the block input before packing, and the layer packs a map a
+    quarter of the size, with a quarter of the resident operands and output polynomials.
 
     The stem (7x7 stride-2 conv on 224x224, then max pooling) is not included: one
     zero-padded 230x230 channel needs N >= 65536 coefficients in this packing.
@@ -144,10 +150,22 @@ def resnet50_body(classes: int = 1000) -> List[object]:
             layers.append(ConvShape(mid, mid, H_in, H_in, f=3, stride=st, pad=1))
             layers.append(ConvShape(mid, out, H_out, H_out, f=1, stride=1, pad=0))
             if b == 0:
-                layers.append(ConvShape(c_in, out, H_in, H_in, f=1, stride=st, pad=0))
+                if st > 1 and subsample_projections:
+                    layers.append(ConvShape(c_in, out, H_out, H_out, f=1, stride=1, pad=0))
+                else:
+                    layers.append(ConvShape(c_in, out, H_in, H_in, f=1, stride=st, pad=0))
             c_in = out
     layers.append(FCShape(2048, classes))
     return layers
+
+
+RESNET50_SUBSAMPLED_PROJECTIONS = (13, 26, 45)   # stride-2 1x1 projections packed on the subsampled map
+
+
+def projection_input(x, stride: int = 2):
+    """The input of a subsampled stride-s 1x1 projection: the pixels of x [c][H][W] at
+    coordinates that are multiples of s."""
+    return x[:, ::stride, ::stride]
 
 
 @dataclass(frozen=True)
