@@ -35,13 +35,13 @@ import workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 CUS, CLOCK_GHZ = 256, 2.4
-# Integer-ALU roofs (whole chip, G operations per second): measured by he_probe_rate
-# (csrc/kernels_probe.hip) and replaced by the run's own measurement when --rates is on (the
-# default).  A Shoup butterfly is 9 vector instructions (1 mul_hi, 2 mul_lo, 6 add / sub / min);
-# the MAC's inner product is one v_mad_u64_u32 per product.
-BFLY_PEAK_G = 4470.0
-GSBFLY_PEAK_G = 4470.0
-MAD64_PEAK_G = 22400.0
+# Integer-ALU roofs (whole chip, G operations per second): he_probe_rate (csrc/kernels_probe.hip)
+# on an MI355X, the figures of profiles/alu_rates_MI355X.md; a run replaces them with its own
+# measurement unless --no-rates.  A Shoup butterfly is 9 vector instructions (1 mul_hi, 2 mul_lo,
+# 6 add / sub / min); the MAC's inner product is one v_mad_u64_u32 per product.
+BFLY_PEAK_G = 4005.8
+GSBFLY_PEAK_G = 4254.0
+MAD64_PEAK_G = 33005.4
 
 
 def alu_rates(he):
@@ -455,12 +455,45 @@ def grouped_form(he, ctx, args, widths, stream, sync):
                          "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                       "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                                       "avg_launch_ms": round(kern_s * 1e3, 3), "kernel": "k_fused_group"}}
-    log(f"grouped: {json.dumps(out)}")
     for g in per_layer:
         g.free()
     whole.free()
     del stacks
     torch.cuda.empty_cache()
+    # single images: every layer of every width once (one image per call, one FC head each), as
+    # captured per-context sequences of layer calls against one grouped launch
+    singles = [Stack(he, ctxs[(8192, 4) if w < 4 else (16384, 6)], wl.CONFIG_BATCHED, w, [10], [1],
+                     8192 if w < 4 else 16384, 4 if w < 4 else 6) for w in widths]
+    seqs = {}
+    for st in singles:
+        for ly, B, c0, sh, shn in st.steps:
+            key = id(st.ctx)
+            if key not in seqs:
+                seqs[key] = he.Sequence(st.ctx)
+            seqs[key].add(ly, c0, sh, shn)
+    sync()
+    with torch.cuda.stream(stream):
+        for q in seqs.values():
+            q.capture(stream)
+        T_seq = time_loop(lambda: [q.replay(stream) for q in seqs.values()], steps * 4, 2, sync)
+    g1 = he.Group()
+    for st in singles:
+        for ly, B, c0, sh, shn in st.steps:
+            g1.add(ly, c0, sh, shn)
+    g1.build()
+    with torch.cuda.stream(stream):
+        T_grp = time_loop(lambda: g1.run(stream), steps * 4, 2, sync)
+    g1.check(stream)
+    il1 = sum(st.image_layers() for st in singles)
+    out["single_images"] = {"calls": len(g1), "sequences_layers_per_s": round(il1 * steps * 4 / T_seq, 1),
+                            "sequences_ms_per_pass": round(T_seq / (steps * 4) * 1e3, 3),
+                            "group_layers_per_s": round(il1 * steps * 4 / T_grp, 1),
+                            "group_ms_per_pass": round(T_grp / (steps * 4) * 1e3, 3),
+                            "group_items_ntt_mac_inverse": list(g1.items()[0])}
+    g1.free()
+    del seqs, singles
+    torch.cuda.empty_cache()
+    log(f"grouped: {json.dumps(out)}")
     return out
 
 
@@ -722,6 +755,8 @@ def main():
     ap.add_argument("--no-resnet50", action="store_true",
                     help="skip the ResNet-50-shaped layers (each distinct shape packed and timed in turn)")
     ap.add_argument("--resnet50-reps", type=int, default=10)
+    ap.add_argument("--batched-tail", type=int, default=None,
+                    help="pin the residue-class tail form of the batched form (HE_TUNE_TAIL value)")
     ap.add_argument("--batched-mac", type=int, default=None,
                     help="pin the MAC variant of the batched form (HE_TUNE_MAC value) instead of tuning it")
     ap.add_argument("--no-served", action="store_true")
@@ -956,6 +991,8 @@ def main():
             bst = Stack(he, bctx, wl.CONFIG_BATCHED, width, [10, 100], [32, 32], N, L)
             if args.batched_mac is not None:
                 bctx.tune_force(he.HE_TUNE_MAC, args.batched_mac)
+            if args.batched_tail is not None:
+                bctx.tune_force(he.HE_TUNE_TAIL, args.batched_tail)
             if not args.no_tune:
                 bst.autotune()
             sync()
@@ -977,6 +1014,8 @@ def main():
             tot_time += T
             if args.batched_mac is not None:
                 bctx.tune_force(he.HE_TUNE_MAC, -1)
+            if args.batched_tail is not None:
+                bctx.tune_force(he.HE_TUNE_TAIL, 0)
             del bseq, bst
             torch.cuda.empty_cache()
         bres["all_widths_layers_per_s"] = round(tot_layers / tot_time, 1)

@@ -1645,7 +1645,7 @@ int he_group_create(const he_layer_call *calls, uint32_t n, uint32_t flags, he_g
         jb.Juse = c.d_sh ? jb.Jtot : jb.K_in;
         jb.ntt_c0 = jb.K_in;
         jb.ntt_sh = c.d_sh ? jb.K_in : 0;
-        jb.no_wide = 1;
+        jb.grouped = 1;
         // image-tiled MAC items: a resident operand word read once per tile of images rather than
         // once per image (automatic from four images up)
         if (jb.kind == FZ_KIND_CONV && flags != HE_GROUP_MAC_PER_IMAGE && (c.B >= 4 || flags == HE_GROUP_MAC_TILED)) {

@@ -151,7 +151,8 @@ struct FusedLayer {
                               // (1024-thread workgroups); 0 = sub-block NTT, MAC chunk and tail items
     uint32_t mac_tiled;       // conv, grouped launch: MAC items are LDS-staged tiles of images x
                               // channels (geometry gm); 0 = one image per MAC item
-    uint32_t no_wide;         // conv: per-image MAC items by channel groups only (grouped launch)
+    uint32_t grouped;         // planned for the grouped launch: per-image conv MAC items by channel
+                              // groups only, tails of 128 threads per vector from 512 points up
     MacLdsGeom gm;
     // filled by fused_layer_plan.  Counters go per image tile of 2^tile_log images (n_tiles of
     // them; one image per tile unless the MAC is tiled)

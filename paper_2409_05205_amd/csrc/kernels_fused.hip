@@ -396,11 +396,11 @@ __device__ __forceinline__ void fz_mac_tile_switch(const FusedLayer &jb, uint32_
 
 // ------------------------------------------------------------------ tail items (conv)
 // The residue-class tail of one output group and limb for RW channel vectors of M = N/s points
-// (the steps of the residue-class tail kernel in kernels_ntt.hip, in a 256-thread item).
-template <int LOGM>
+// (the steps of the residue-class tail kernel in kernels_ntt.hip, in a 256-thread item).  LOGR
+// words per thread (T = M / 2^LOGR threads per vector); TWB sizes the twiddle prefetch (PassTw).
+template <int LOGM, int LOGR = (LOGM - 8 > 2 ? LOGM - 8 : 2), int TWB = FZ_THREADS>
 __device__ __forceinline__ void fz_tail_item(const FusedLayer &jb, uint32_t it, uint32_t *lds, const uint32_t *__restrict__ twi,
                              const uint32_t *__restrict__ twish, const LimbConsts &lc, uint32_t *ctr, uint32_t *err) {
-    constexpr int LOGR = LOGM - 8 > 2 ? LOGM - 8 : 2;
     constexpr int M = 1 << LOGM;
     constexpr int T = 1 << (LOGM - LOGR);
     constexpr int MP = M + (M >> 5);
@@ -427,8 +427,8 @@ __device__ __forceinline__ void fz_tail_item(const FusedLayer &jb, uint32_t it, 
     const bool exists = active && n < c_o;
     const uint32_t *W = twi + (size_t)l * N;
     const uint32_t *Wsh = twish + (size_t)l * N;
-    PassTw<LOGM, LOGR, FZ_THREADS> ptw;
-    inv_tw_load<LOGM, LOGR, FZ_THREADS, 0>(ptw, t, W, Wsh);
+    PassTw<LOGM, LOGR, TWB> ptw;
+    inv_tw_load<LOGM, LOGR, TWB, 0>(ptw, t, W, Wsh);
     const uint32_t cw_log = s_log - (31u - __clz(g_o));
     const uint32_t span_log = (31u - __clz(RW)) + cw_log;
     const uint32_t c_lo = np0 << cw_log;
@@ -454,7 +454,7 @@ __device__ __forceinline__ void fz_tail_item(const FusedLayer &jb, uint32_t it, 
     }
     __syncthreads();
     uint32_t v[1 << LOGR];
-    inv_pass<LOGM, LOGR, FZ_THREADS, 0>(v, ptw, my, t, W, Wsh, c.q, c.q2, active);
+    inv_pass<LOGM, LOGR, TWB, 0>(v, ptw, my, t, W, Wsh, c.q, c.q2, active);
     __syncthreads();
     if (active) {
 #pragma unroll
@@ -507,6 +507,29 @@ __device__ __forceinline__ void fz_tail_switch(const FusedLayer &jb, uint32_t it
         case 12: fz_tail_item<12>(jb, it, lds, twi, twish, lc, ctr, err); break;
         default: break;   // excluded by the host (fused_layer_ok)
     }
+}
+
+// Tails in the grouped launch: 128 threads per vector from 512 points up (two or more vectors per
+// item, as the batched tail kernel takes them), twiddles read per pass (registers go to occupancy).
+constexpr int fz_group_tail_logr(int logm) { return logm >= 9 ? logm - 7 : 2; }
+
+__device__ __forceinline__ void fz_tail_switch_group(const FusedLayer &jb, uint32_t it, uint32_t *lds,
+                                                     const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,
+                                                     uint32_t *ctr, uint32_t *err) {
+#define FZ_GT(LM) fz_tail_item<LM, fz_group_tail_logr(LM), TW_IN_PASS>(jb, it, lds, twi, twish, lc, ctr, err)
+    switch (jb.logN - jb.s_log) {
+        case 4: FZ_GT(4); break;
+        case 5: FZ_GT(5); break;
+        case 6: FZ_GT(6); break;
+        case 7: FZ_GT(7); break;
+        case 8: FZ_GT(8); break;
+        case 9: FZ_GT(9); break;
+        case 10: FZ_GT(10); break;
+        case 11: FZ_GT(11); break;
+        case 12: FZ_GT(12); break;
+        default: break;   // excluded by the host (fused_layer_ok)
+    }
+#undef FZ_GT
 }
 
 // ------------------------------------------------------------------ FC items
@@ -922,9 +945,9 @@ k_fused_group(const FusedJob *__restrict__ jobs, uint32_t n_jobs, uint32_t c0, u
         else if (jb.mac_tiled)
             fz_mac_tile_switch(jb, it, lds, lc, ctr, err);
         else
-            fz_mac_conv_item(jb, it, lc, ctr, err);   // no_wide: the plan gave ng >= 1
+            fz_mac_conv_item(jb, it, lc, ctr, err);   // grouped: the plan gave ng >= 1
     } else {
-        fz_tail_switch(jb, it, lds, J.twi, J.twish, lc, ctr, err);
+        fz_tail_switch_group(jb, it, lds, J.twi, J.twish, lc, ctr, err);
     }
 }
 
@@ -977,22 +1000,26 @@ uint32_t fused_layer_plan(FusedLayer &jb) {
             jb.n_tiles = jb.gm.tiles_b;
             jb.mac_per_bl = jb.gm.ranges * jb.gm.tiles_n;
             jb.n_mac = jb.L * jb.gm.ranges * jb.gm.tiles_b * jb.gm.tiles_n;
-        } else if (!jb.no_wide && (jb.Juse == 1 || jb.Juse == 2 || jb.Juse == 4 || jb.Juse == 8) && jb.s_log <= 7) {
+        } else if (!jb.grouped && (jb.Juse == 1 || jb.Juse == 2 || jb.Juse == 4 || jb.Juse == 8) && jb.s_log <= 7) {
             // every channel of a 128-slot chunk per item (ng = 0 marks this form)
             jb.ng = 0;
             jb.mac_per_bl = N / FZ_WCHUNK;
             jb.n_mac = jb.B * jb.L * jb.mac_per_bl;
         } else {
-            // channels per MAC item: about a thousand items, up to 4 channels each
+            // channels per MAC item: about a thousand items, up to 4 channels each; in a grouped
+            // launch (many calls' items at once) 8 channels, fewer and longer items
             const uint64_t base = (uint64_t)jb.B * jb.L * chunks * jb.rows;
             uint32_t ng = 1;
-            while (ng < 4 && base / (2 * ng) >= 1024) ng <<= 1;
+            if (jb.grouped)
+                ng = jb.rows < 8 ? jb.rows : 8;
+            else
+                while (ng < 4 && base / (2 * ng) >= 1024) ng <<= 1;
             jb.ng = ng;
             jb.mac_per_bl = chunks * ((jb.rows + ng - 1) / ng);
             jb.n_mac = jb.B * jb.L * jb.mac_per_bl;
         }
         const uint32_t logm = jb.logN - jb.s_log;
-        const uint32_t logr = logm > 10 ? logm - 8 : 2;
+        const uint32_t logr = jb.grouped ? (uint32_t)fz_group_tail_logr((int)logm) : (logm > 10 ? logm - 8 : 2);
         const uint32_t T = 1u << (logm - logr);
         uint32_t rw = FZ_THREADS / T;
         if (rw > jb.g_o) rw = jb.g_o;
