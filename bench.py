@@ -425,6 +425,10 @@ def grouped_form(he, ctx, args, widths, stream, sync):
         for ly, B, c0, sh, shn in st.steps:
             whole.add(ly, c0, sh, shn)
     whole.build()
+    if not args.no_tune:
+        for g in per_layer:
+            g.tune(stream)
+        whole.tune(stream)
     il = sum(st.image_layers() for st in stacks)
     nbytes = sum(st.layer_bytes() for st in stacks)
     steps = args.batched_steps
@@ -450,6 +454,7 @@ def grouped_form(he, ctx, args, widths, stream, sync):
     kern_s = ms / 1e3 / max(1, n)
     gbs = nbytes / kern_s / 1e9
     out["one_launch"] = {"launches_per_pass": 1, "calls": len(whole), "layers_per_s": round(il * steps / T, 1),
+                         "xcd_chunk": 1 << whole.chunk_log,
                          "ms_per_pass": round(T / steps * 1e3, 3), "items_ntt_mac_inverse": list(items),
                          "image_tiled_calls": tiled, "workspace_bytes": ws,
                          "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
@@ -481,6 +486,8 @@ def grouped_form(he, ctx, args, widths, stream, sync):
         for ly, B, c0, sh, shn in st.steps:
             g1.add(ly, c0, sh, shn)
     g1.build()
+    if not args.no_tune:
+        g1.tune(stream)
     with torch.cuda.stream(stream):
         T_grp = time_loop(lambda: g1.run(stream), steps * 4, 2, sync)
     g1.check(stream)

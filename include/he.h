@@ -374,6 +374,14 @@ void he_seq_free(he_seq *seq);
  * the flag is cleared), else HE_OK.
  * he_group_items -- work items per phase (NTT, MAC, inverse), the number of
  * calls whose MAC runs in image tiles, and the workspace bytes.
+ * he_group_tune -- the autotuner's knob of a group: the items of a phase go
+ * to the 8 XCDs in chunks of 2^c consecutive items, round robin (neighbouring
+ * items of one call share an L2; calls of different cost spread over every
+ * XCD).  Times one launch per candidate c in 2..8 (median of three after a
+ * warm-up, on `stream`, synchronising), keeps the fastest and returns it in
+ * *chunk_log (may be NULL); the launches write the calls' outputs (the same
+ * words each time).  Then as he_group_check.  Default before tuning: c = 6.
+ * he_group_set_chunk -- sets c (0..10) directly.
  */
 typedef struct {
     he_ctx *ctx;
@@ -388,6 +396,8 @@ int he_group_create(const he_layer_call *calls, uint32_t n, uint32_t flags, he_g
 int he_group_run(he_group *g, void *stream);
 int he_group_check(he_group *g, void *stream);
 int he_group_items(const he_group *g, uint32_t *items, uint32_t *tiled_jobs, size_t *workspace_bytes);
+int he_group_tune(he_group *g, void *stream, uint32_t *chunk_log);
+int he_group_set_chunk(he_group *g, uint32_t chunk_log);
 void he_group_free(he_group *g);
 
 /*

@@ -1591,6 +1591,7 @@ struct he_group {
     uint32_t *sync = nullptr;            // header + every job's counters, zero between launches
     size_t ws_bytes = 0, sync_words = 0;
     uint32_t count[3] = {0, 0, 0};
+    uint32_t chunk_log = 6;              // items per XCD chunk of a phase: 2^chunk_log (he_group_tune)
 };
 
 namespace {
@@ -1713,10 +1714,61 @@ int he_group_create(const he_layer_call *calls, uint32_t n, uint32_t flags, he_g
 int he_group_run(he_group *g, void *stream) {
     if (!g) return HE_EINVAL;
     ProfScope ps(g->ctx0, HE_K_GROUP);
-    hipError_t e = launch_fused_group(g->d_jobs, (uint32_t)g->jobs.size(), g->count, g->sync, (hipStream_t)stream,
-                                      ps.ev());
+    hipError_t e = launch_fused_group(g->d_jobs, (uint32_t)g->jobs.size(), g->count, g->chunk_log, g->sync,
+                                      (hipStream_t)stream, ps.ev());
     if ((e = ps.done(e)) != hipSuccess) return dev_fail(e, "grouped layer launch");
     return HE_OK;
+}
+
+int he_group_set_chunk(he_group *g, uint32_t chunk_log) {
+    if (!g || chunk_log > 10) return HE_EINVAL;
+    g->chunk_log = chunk_log;
+    return HE_OK;
+}
+
+int he_group_tune(he_group *g, void *stream, uint32_t *chunk_log) {
+    if (!g) return HE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HE_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return HE_EDEVICE;
+    }
+    int rc = HE_OK;
+    uint32_t best = g->chunk_log;
+    float best_ms = 0.f;
+    for (uint32_t c : {2u, 3u, 4u, 5u, 6u, 7u, 8u}) {
+        g->chunk_log = c;
+        float t[3];
+        for (int r = -1; r < 3 && rc == HE_OK; ++r) {
+            // a warm-up launch, then three timed ones (the median is kept)
+            if (hipEventRecord(e0, st) != hipSuccess) rc = HE_EDEVICE;
+            if (rc == HE_OK && launch_fused_group(g->d_jobs, (uint32_t)g->jobs.size(), g->count, c, g->sync, st) !=
+                                   hipSuccess)
+                rc = HE_EDEVICE;
+            if (rc == HE_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = HE_EDEVICE;
+            float ms = 0.f;
+            if (rc == HE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = HE_EDEVICE;
+            if (r >= 0) t[r] = ms;
+        }
+        if (rc != HE_OK) break;
+        std::sort(t, t + 3);
+        if (best_ms == 0.f || t[1] < best_ms) {
+            best_ms = t[1];
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->chunk_log = best;
+    if (rc != HE_OK) {
+        g_last_error = "he_group_tune: a timed launch failed";
+        return rc;
+    }
+    if (chunk_log) *chunk_log = best;
+    return he_group_check(g, stream);
 }
 
 int he_group_check(he_group *g, void *stream) {

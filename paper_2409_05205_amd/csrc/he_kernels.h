@@ -180,9 +180,10 @@ struct FusedJob {
 };
 // Largest LDS need (bytes) of a tiled MAC item the grouped launch accepts.
 uint32_t fused_group_lds_bytes();
-// jobs: device array of n_jobs entries; count[p]: items of phase p over all jobs.
-hipError_t launch_fused_group(const FusedJob *jobs, uint32_t n_jobs, const uint32_t count[3], uint32_t *sync,
-                              hipStream_t st, const LaunchEv *ev = nullptr);
+// jobs: device array of n_jobs entries; count[p]: items of phase p over all jobs; the items of a
+// phase go to the XCDs in chunks of 2^chunk_log (0..10).
+hipError_t launch_fused_group(const FusedJob *jobs, uint32_t n_jobs, const uint32_t count[3], uint32_t chunk_log,
+                              uint32_t *sync, hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Client masks from the server's resident operands (kernels_client.hip): noise rows into the
 // operand layout, then the combination with NTT(b) (in place on E).

@@ -887,39 +887,44 @@ k_fused_layer(FusedLayer jb, const uint32_t *__restrict__ tw, const uint32_t *__
 // The items of every job, phase by phase: all NTT items, then all MAC items, then all tail
 // items, so that an item waits only for items of earlier phases, which have lower workgroup ids
 // (the argument at the top of the file).  Phase p takes 8 per_p workgroups from a multiple of 8;
-// within a phase the ids are remapped as by xcd_logical, so that neighbouring items of one job
-// (the sub-blocks of one row, the slot ranges of one tile) share an XCD and its L2; workgroups
-// past the phase's item count return at once.  The job of an item is found by a binary search
-// over the jobs' first items of that phase.
+// within a phase the items go to the XCDs in chunks of 2^chunk_log consecutive items, round
+// robin, so that neighbouring items of one job (the sub-blocks of one row, the slot ranges of one
+// tile) share an XCD and its L2 while the jobs, which differ widely in cost, spread over every
+// XCD (the chunk is a tuning knob of the group); workgroups past the phase's item count return
+// at once.  The job of an item is found by a binary search over the jobs' first items of that
+// phase.
 // Three workgroups per CU (at most 168 VGPRs, what the tiled MAC item takes alone): the MAC and
 // inverse items of batched calls need the occupancy, so the NTT items keep fewer twiddles in
 // registers than in the one-layer launch, and a per-image MAC takes the channel-group item (the
 // all-channel item holds too many operand words in registers).
 constexpr int FG_LDS = 6656;   // words: the largest tiled MAC stage pair (2 x 24 rows x 34 words) and more
 constexpr int FG_TWB = 1024;
+// Workgroups per XCD of a phase of `count` items (whole chunks of 2^chunk_log).
+__host__ __device__ constexpr uint32_t fg_per_xcd(uint32_t count, uint32_t chunk_log) {
+    return ((count + (8u << chunk_log) - 1u) >> (chunk_log + 3u)) << chunk_log;
+}
 static_assert(FG_LDS >= FZ_LDS, "the group's LDS holds every item's");
 
 __global__ void __launch_bounds__(FZ_THREADS, 3)
 k_fused_group(const FusedJob *__restrict__ jobs, uint32_t n_jobs, uint32_t c0, uint32_t c1, uint32_t c2,
-              uint32_t *__restrict__ sync) {
+              uint32_t chunk_log, uint32_t *__restrict__ sync) {
     __shared__ __align__(16) uint32_t lds[FG_LDS];   // 16-byte aligned: the tiled MAC reads 8-byte pairs
-    const uint32_t p0 = (c0 + 7u) >> 3, p1 = (c1 + 7u) >> 3, p2 = (c2 + 7u) >> 3;
-    uint32_t t = blockIdx.x, phase, count, per;
+    const uint32_t p0 = fg_per_xcd(c0, chunk_log), p1 = fg_per_xcd(c1, chunk_log);
+    uint32_t t = blockIdx.x, phase, count;
     if (t < 8u * p0) {
         phase = 0;
         count = c0;
-        per = p0;
     } else if ((t -= 8u * p0) < 8u * p1) {
         phase = 1;
         count = c1;
-        per = p1;
     } else {
         t -= 8u * p1;
         phase = 2;
         count = c2;
-        per = p2;
     }
-    const uint32_t item = (t & 7u) * per + (t >> 3);
+    // XCD x's k-th workgroup of the phase takes item k mod 2^chunk_log of chunk (k >> chunk_log) 8 + x
+    const uint32_t k = t >> 3;
+    const uint32_t item = ((((k >> chunk_log) << 3) + (t & 7u)) << chunk_log) + (k & ((1u << chunk_log) - 1u));
     if (item >= count) return;
     uint32_t lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -1080,12 +1085,15 @@ hipError_t launch_fused_layer(const FusedLayer &jb, const uint32_t *tw, const ui
 
 uint32_t fused_group_lds_bytes() { return (uint32_t)FG_LDS * 4u; }
 
-hipError_t launch_fused_group(const FusedJob *jobs, uint32_t n_jobs, const uint32_t count[3], uint32_t *sync,
-                              hipStream_t st, const LaunchEv *ev) {
+hipError_t launch_fused_group(const FusedJob *jobs, uint32_t n_jobs, const uint32_t count[3], uint32_t chunk_log,
+                              uint32_t *sync, hipStream_t st, const LaunchEv *ev) {
     if (n_jobs == 0) return hipSuccess;
-    const uint32_t grid = xcd_grid(count[0]) + xcd_grid(count[1]) + xcd_grid(count[2]);
+    if (chunk_log > 10) return hipErrorInvalidValue;
+    const uint64_t grid = 8ull * ((uint64_t)fg_per_xcd(count[0], chunk_log) + fg_per_xcd(count[1], chunk_log) +
+                                  fg_per_xcd(count[2], chunk_log));
     if (grid == 0) return hipSuccess;
-    HE_LAUNCH(ev, k_fused_group, dim3(grid), dim3(FZ_THREADS), 0, st, jobs, n_jobs, count[0], count[1], count[2],
-              sync);
+    if (grid > 0x7fffffffull) return hipErrorInvalidValue;
+    HE_LAUNCH(ev, k_fused_group, dim3((uint32_t)grid), dim3(FZ_THREADS), 0, st, jobs, n_jobs, count[0], count[1],
+              count[2], chunk_log, sync);
     return hipGetLastError();
 }

@@ -36,7 +36,8 @@ EXPORTED = [
     "he_pack_operands", "he_client_masks", "he_encrypt_c0", "he_decrypt", "he_server_add_request_after",
     "he_layer_geometry", "he_ctx_workspace_bytes", "he_workspace_reserve", "he_conv_layer_noalloc",
     "he_sync_check", "he_probe_rate",
-    "he_group_create", "he_group_run", "he_group_check", "he_group_items", "he_group_free",
+    "he_group_create", "he_group_run", "he_group_check", "he_group_items", "he_group_free", "he_group_tune",
+    "he_group_set_chunk",
 ]
 HE_PROBE_BFLY, HE_PROBE_GSBFLY, HE_PROBE_MAD64, HE_PROBE_ADD, HE_PROBE_MULLO, HE_PROBE_MULHI = 1, 2, 3, 4, 5, 6
 NOALLOC_SCRATCH_BYTES = 32 << 20   # HE_NOALLOC_SCRATCH_BYTES in include/he.h
@@ -150,6 +151,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.he_group_check.argtypes = [VP, VP]
     lib.he_group_items.argtypes = [VP, P(U32), P(U32), P(SZ)]
     lib.he_group_free.argtypes = [VP]
+    lib.he_group_tune.argtypes = [VP, VP, P(U32)]
+    lib.he_group_set_chunk.argtypes = [VP, U32]
     lib.he_free_layer.argtypes = [VP]
     lib.he_free.argtypes = [VP]
     lib.he_strerror.argtypes = [ctypes.c_int]
@@ -627,6 +630,7 @@ class Group:
 
     def __init__(self):
         self.handle = None
+        self.chunk_log = 6
         self._calls = []
         self._keep = []
 
@@ -666,6 +670,17 @@ class Group:
 
     def check(self, stream=None):
         _check(load_library().he_group_check(self.handle, _stream(stream)), "he_group_check")
+
+    def tune(self, stream=None) -> int:
+        """he_group_tune: time each XCD chunk size, keep the fastest; returns its log2."""
+        c = ctypes.c_uint32()
+        _check(load_library().he_group_tune(self.handle, _stream(stream), ctypes.byref(c)), "he_group_tune")
+        self.chunk_log = int(c.value)
+        return self.chunk_log
+
+    def set_chunk(self, chunk_log: int):
+        _check(load_library().he_group_set_chunk(self.handle, chunk_log), "he_group_set_chunk")
+        self.chunk_log = chunk_log
 
     def items(self):
         """(work items per phase (NTT, MAC, inverse), calls with image-tiled MAC, workspace bytes)."""

@@ -7,7 +7,8 @@ last-layer pattern; each image's words must equal the oracle's server evaluation
 Alg. 2), under each MAC item form (automatic, one image per item, image tiles).  Full size: one
 launch holding the batch-64 layers of the x1, x2 and x4 variants (N = 8192 / 16384) must give the
 oracle's stored digests of the sampled images, and plain-20 layers of both ring degrees must give
-the words of the one-call path.  Repeated launches check that the counters return to zero.
+the words of the one-call path.  Repeated launches check that the counters return to zero, under
+several ways of dealing the items to the XCDs and after the group's autotuner ran.
 """
 import json
 import os
@@ -98,9 +99,11 @@ def test_group_small_rings_match_oracle(he, flags):
         assert tiled == 0
     if flags == 2:
         assert tiled == sum(1 for c in SMALL if c[1] == "conv")
-    for rep in range(3):
+    # three launches in a row, with the items dealt to the XCDs in chunks of 64, 1 and 1024
+    for rep, chunk_log in enumerate((6, 0, 10)):
         for o in outs:
             o.fill_(-1)
+        grp.set_chunk(chunk_log)
         grp.run()
         grp.check()
         for i, (o, want) in enumerate(zip(outs, wants)):
@@ -133,8 +136,11 @@ def test_group_batched_widths_one_launch(he):
         outs.append((name, images, out))
     grp.build()
     items, tiled, ws = grp.items()
-    print(f"items {items} tiled calls {tiled} workspace {ws / 2**20:.0f} MiB", flush=True)
-    assert tiled == len(cases.BATCHED_SAMPLES)
+    chunk_log = grp.tune()
+    print(f"items {items} tiled calls {tiled} workspace {ws / 2**20:.0f} MiB, tuned chunk 2^{chunk_log}", flush=True)
+    assert tiled == len(cases.BATCHED_SAMPLES) and 2 <= chunk_log <= 8
+    for _, _, out in outs:
+        out.fill_(-1)
     for rep in range(2):
         grp.run()
         grp.check()
