@@ -1651,9 +1651,9 @@ int he_group_create(const he_layer_call *calls, uint32_t n, uint32_t flags, he_g
         // once per image (automatic from four images up)
         if (jb.kind == FZ_KIND_CONV && flags != HE_GROUP_MAC_PER_IMAGE && (c.B >= 4 || flags == HE_GROUP_MAC_TILED)) {
             MacLdsGeom gm;
-            size_t lds = 0;
-            if (mac_lds_geometry(c.B, c.layer->n_rows, in.N, in.s, &gm, &lds, 32) && lds <= fused_group_lds_bytes() &&
-                (size_t)gm.R * gm.cpb <= in.N / 4) {
+            size_t lds_pad = 0;
+            if (mac_lds_geometry(c.B, c.layer->n_rows, in.N, in.s, &gm, &lds_pad, 64) &&
+                (size_t)gm.R * gm.cpb <= in.N / 4 && mac_dma_lds_bytes(gm) <= fused_group_lds_bytes()) {
                 jb.mac_tiled = 1;
                 jb.gm = gm;
             }

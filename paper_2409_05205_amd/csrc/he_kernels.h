@@ -114,6 +114,9 @@ bool mac_lds_geometry(uint32_t B, uint32_t c_o, uint32_t N, uint32_t s, MacLdsGe
 hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
                           uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool xcd_order,
                           const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
+// LDS bytes of the DMA-staged form for geometry gm (from mac_lds_geometry with 64-slot short
+// stages), or SIZE_MAX when the form cannot take it.
+size_t mac_dma_lds_bytes(const MacLdsGeom &gm);
 // Same products and output as launch_mac_lds, with the stages moved to LDS by global_load_lds
 // (three stage buffers, no register staging).
 hipError_t launch_mac_dma(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,

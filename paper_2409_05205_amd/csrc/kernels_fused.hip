@@ -127,19 +127,20 @@ __device__ __forceinline__ uint32_t fz_tile_imgs(const FusedLayer &jb, uint32_t 
 
 // ------------------------------------------------------------------ NTT items
 // TWB: the workgroup size the twiddle prefetch is sized for (PassTw); a larger value keeps fewer
-// twiddles in registers.
-template <int LOGN, int TWB = FZ_THREADS>
+// twiddles in registers.  K: the row is transformed as 2^K sub-blocks of N / 2^K points, one per
+// item (K = 0: the whole row); an item counts itself done for each quarter of the row it covers.
+template <int LOGN, int TWB = FZ_THREADS, int K = 2>
 __device__ __forceinline__ void fz_ntt_item(const FusedLayer &jb, uint32_t it, uint32_t *lds, const uint32_t *__restrict__ tw,
                             const uint32_t *__restrict__ twsh, const LimbConsts &lc, uint32_t *ctr) {
-    constexpr int K = 2;
+    static_assert(K >= 0 && K <= 2, "whole rows, halves or quarters");
     constexpr int LS = LOGN - K;
     constexpr int NS = 1 << LS;
     constexpr int LOGR = LS - 8;                     // 256 threads per sub-block
     constexpr int T = 1 << (LS - LOGR);
     static_assert(T == FZ_THREADS, "one sub-block per workgroup");
     const uint32_t tid = threadIdx.x;
-    const uint32_t sub = it & 3u;
-    uint32_t r = it >> 2;
+    const uint32_t sub = it & ((1u << K) - 1u);
+    uint32_t r = it >> K;
     const uint32_t L = jb.L;
     const uint32_t l = r % L;
     r /= L;
@@ -173,8 +174,20 @@ __device__ __forceinline__ void fz_ntt_item(const FusedLayer &jb, uint32_t it, u
         y = csub(y, q2);
         st_dev(out + idx, csub(y, q));
     }
-    fz_signal(ctr + (((b >> jb.tile_log) * L + l) * 4u + sub) * jb.ctr_stride, 1u);
+    stores_done();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *c4 = ctr + ((b >> jb.tile_log) * L + l) * 4u * jb.ctr_stride;
+#pragma unroll
+        for (int qq = 0; qq < (4 >> K); ++qq)
+            __hip_atomic_fetch_add(c4 + ((sub << (2 - K)) + qq) * jb.ctr_stride, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
+
+// Sub-blocks per row of the grouped launch's NTT items: whole rows up to 8192 points (the group's
+// LDS holds one), halves of a 16384-point row.
+constexpr int fz_group_ntt_k(int logn) { return logn > 13 ? logn - 13 : 0; }
 
 // ------------------------------------------------------------------ MAC items (conv)
 // The per-image MAC items below run with one image per counter tile (tile_log = 0).
@@ -361,9 +374,9 @@ __device__ __forceinline__ void fz_mac_wide_switch(const FusedLayer &jb, uint32_
 }
 
 // ------------------------------------------------------------------ MAC items, image tiles (conv)
-// Grouped launch at larger batches: one LDS-staged tile of the batched MAC (images x channels of
-// one limb over a range of slots, mac_device.h) per item, so that a resident operand word is read
-// once per tile of images instead of once per image.  It waits for the NTT sub-block holding its
+// Grouped launch at larger batches: one tile of the batched MAC staged in LDS by DMA (images x
+// channels of one limb over a range of slots, mac_device.h) per item, so that a resident operand
+// word is read once per tile of images instead of once per image.  It waits for the NTT sub-block holding its
 // slot range for every image of its tile (one counter per tile), stores its block sums with
 // device scope and counts itself done for the tile.
 template <int GS>
@@ -379,7 +392,7 @@ __device__ __forceinline__ void fz_mac_tile_item(const FusedLayer &jb, uint32_t 
     const uint32_t l = w / gm.ranges;
     const uint32_t sub = (range * gm.R * gm.cpb) >> (jb.logN - 2);
     fz_wait(ctr + ((bt * L + l) * 4u + sub) * jb.ctr_stride, fz_tile_imgs(jb, bt) * (jb.ntt_c0 + jb.ntt_sh), err);
-    mac_lds_tile<GS, true>(jb.x, jb.op, jb.h, jb.B, jb.Jtot, jb.Juse, jb.rows, L, 1u << jb.logN, jb.s_log, gm, it,
+    mac_dma_tile<GS, true>(jb.x, jb.op, jb.h, jb.B, jb.Jtot, jb.Juse, jb.rows, L, 1u << jb.logN, jb.s_log, gm, it,
                            lds, lc);
     fz_signal(ctr + (jb.n_tiles * L * 4u + bt * L + l) * jb.ctr_stride, 1u);
 }
@@ -893,19 +906,23 @@ k_fused_layer(FusedLayer jb, const uint32_t *__restrict__ tw, const uint32_t *__
 // XCD (the chunk is a tuning knob of the group); workgroups past the phase's item count return
 // at once.  The job of an item is found by a binary search over the jobs' first items of that
 // phase.
-// Three workgroups per CU (at most 168 VGPRs, what the tiled MAC item takes alone): the MAC and
-// inverse items of batched calls need the occupancy, so the NTT items keep fewer twiddles in
-// registers than in the one-layer launch, and a per-image MAC takes the channel-group item (the
-// all-channel item holds too many operand words in registers).
-constexpr int FG_LDS = 6656;   // words: the largest tiled MAC stage pair (2 x 24 rows x 34 words) and more
+// Four workgroups per CU (at most 128 VGPRs; the LDS of four fits a CU): the MAC and inverse items
+// of batched calls need the occupancy, so the NTT items keep fewer twiddles in registers than in
+// the one-layer launch, the tiled MAC item is the DMA-staged one (no staging registers), and a
+// per-image MAC takes the channel-group item (the all-channel item holds too many operand words
+// in registers).  A few bytes per lane spill at this cap; three workgroups per CU without the
+// spill ran the three batched stacks 8 % slower.
+// words: the three DMA stage buffers of the largest tile geometry (3 x 96 rows x 32 words), more
+// than an 8192-point row
+constexpr int FG_LDS = 9216;
 constexpr int FG_TWB = 1024;
 // Workgroups per XCD of a phase of `count` items (whole chunks of 2^chunk_log).
 __host__ __device__ constexpr uint32_t fg_per_xcd(uint32_t count, uint32_t chunk_log) {
     return ((count + (8u << chunk_log) - 1u) >> (chunk_log + 3u)) << chunk_log;
 }
-static_assert(FG_LDS >= FZ_LDS, "the group's LDS holds every item's");
+static_assert(FG_LDS >= FZ_LDS && FG_LDS >= 8192 + 256, "the group's LDS holds every item's");
 
-__global__ void __launch_bounds__(FZ_THREADS, 3)
+__global__ void __launch_bounds__(FZ_THREADS, 4)
 k_fused_group(const FusedJob *__restrict__ jobs, uint32_t n_jobs, uint32_t c0, uint32_t c1, uint32_t c2,
               uint32_t chunk_log, uint32_t *__restrict__ sync) {
     __shared__ __align__(16) uint32_t lds[FG_LDS];   // 16-byte aligned: the tiled MAC reads 8-byte pairs
@@ -940,9 +957,9 @@ k_fused_group(const FusedJob *__restrict__ jobs, uint32_t n_jobs, uint32_t c0, u
     uint32_t *ctr = sync + FZ_SB_HDR + J.ctr_off;
     if (phase == 0) {
         switch (jb.logN) {
-            case 12: fz_ntt_item<12, FG_TWB>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
-            case 13: fz_ntt_item<13, FG_TWB>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
-            default: fz_ntt_item<14, FG_TWB>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
+            case 12: fz_ntt_item<12, FG_TWB, fz_group_ntt_k(12)>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
+            case 13: fz_ntt_item<13, FG_TWB, fz_group_ntt_k(13)>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
+            default: fz_ntt_item<14, FG_TWB, fz_group_ntt_k(14)>(jb, it, lds, J.tw, J.twsh, lc, ctr); break;
         }
     } else if (phase == 1) {
         if (jb.kind != FZ_KIND_CONV)
@@ -996,7 +1013,7 @@ uint32_t fused_layer_plan(FusedLayer &jb) {
         jb.ctr_stride = (FZ_SB_HDR + jb.n_ctr * 32u <= FZ_SYNC_WORDS) ? 32u : 1u;
         return jb.n_ctr * jb.ctr_stride;
     }
-    jb.n_ntt = jb.B * (jb.ntt_c0 + jb.ntt_sh) * jb.L * 4u;
+    jb.n_ntt = jb.B * (jb.ntt_c0 + jb.ntt_sh) * jb.L * (jb.grouped ? (1u << fz_group_ntt_k((int)jb.logN)) : 4u);
     if (jb.kind == FZ_KIND_CONV) {
         if (jb.mac_tiled) {
             // LDS-staged tiles of 4 TBq images (one counter tile each) x 4 TNq channels

@@ -197,175 +197,16 @@ k_mac_lds(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint3
     mac_lds_tile<GS, false>(X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, w, lds, lc);
 }
 
-// ------------------------------------------------------------------ batched MAC, staged by LDS DMA
-// The products of k_mac_lds with the stages brought in by global_load_lds_dwordx4: a lane's 16
-// bytes go straight from memory to LDS (at the wave's base + 16 lane), so a stage takes no
-// registers and no store pass, and three stage buffers keep two stages in flight during the
-// products.  Rows are not padded (a wave's lanes fill contiguous LDS); instead the 16-byte chunks
-// of a row are permuted by an XOR with bits of the row index, so that the rows a wave reads at
-// one column fall in different banks.  A wave waits for its own loads of the stage with a
-// load-count wait and then meets the others at a plain barrier, which leaves the newer stage's
-// loads in flight.
-__device__ __forceinline__ void wait_loads_at_most(uint32_t n) {
-    // s_waitcnt with vmcnt = n and the other counters at their maxima
-    switch (n) {
-        case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
-        case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
-        case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
-        case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
-        default: __builtin_amdgcn_s_waitcnt(0x0F74); break;
-    }
-}
-
-constexpr int MD_BUFS = 3;
-
+// (mac_device.h holds the tile body.)
 template <int GS>
 __global__ void __launch_bounds__(ML_THREADS)
 k_mac_dma(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ h, uint32_t B,
           uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s_log, MacLdsGeom gm,
           uint32_t xcd_order, LimbConsts lc) {
     extern __shared__ uint32_t lds[];
-    const uint32_t TBq = gm.TBq, TNq = gm.TNq, TB = 4 * TBq, TN = 4 * TNq, R = gm.R;
-    const uint32_t R4 = R >> 2, r4_log = 31u - __clz(R4);
-    // rows whose starts share a bank (R words apart, 32 banks) get distinct chunk permutations;
-    // at R >= 32 every row starts on bank 0 and the low row bits spread 8 rows over the banks
-    const uint32_t sw_shift = R >= 32 ? 0u : 5u - (31u - __clz(R));
-    const uint32_t buf_words = (TB + TN) * R;
     uint32_t w = blockIdx.x;
     if (xcd_order && !xcd_logical(blockIdx.x, L * gm.ranges * gm.tiles_b * gm.tiles_n, w)) return;
-    const uint32_t tb = w % gm.tiles_b;
-    w /= gm.tiles_b;
-    const uint32_t tn = w % gm.tiles_n;
-    w /= gm.tiles_n;
-    const uint32_t range = w % gm.ranges;
-    const uint32_t l = w / gm.ranges;
-    const uint32_t b0 = tb * TB, n0 = tn * TN;
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    const uint32_t sub = tid % (TBq * TNq);
-    const uint32_t g = tid / (TBq * TNq);
-    const uint32_t bi = sub / TNq, ni = sub % TNq;
-    const LimbConst c = lc.l[l];
-    const uint32_t cpb = gm.cpb, gpb = gm.gpb;   // (locals: the lambdas below capture by reference)
-    const uint32_t base = range * R * cpb;
-    const uint32_t stages = Juse * cpb;
-    const uint32_t units = (TB + TN) * R4;
-    // load instructions this wave issues per stage (the same for every stage)
-    uint32_t nld = 0;
-#pragma unroll
-    for (int i = 0; i < ML_UNITS; ++i) nld += (i * ML_THREADS + 64u * wave < units) ? 1u : 0u;
-
-    // slot u of a stage buffer holds chunk (u mod R4) ^ swz(row) of row u / R4 (x rows first,
-    // then operand rows) of input row J = st / cpb
-    auto issue = [&](uint32_t st, uint32_t buf) {
-        const uint32_t J = st / cpb, k_st = base + (st % cpb) * R;
-        uint32_t *dst = lds + buf * buf_words;
-#pragma unroll
-        for (int i = 0; i < ML_UNITS; ++i) {
-            const uint32_t u0 = i * ML_THREADS + 64u * wave;   // first slot of this wave's lanes
-            if (u0 < units) {
-                const uint32_t u = u0 + lane;
-                const uint32_t uc = u < units ? u : units - 1u;
-                const uint32_t row = uc >> r4_log;
-                const uint32_t chunk = (uc & (R4 - 1u)) ^ ((row >> sw_shift) & (R4 - 1u));
-                const uint32_t k = k_st + chunk * 4u;
-                // both candidate addresses as integers, then one select (a per-lane choice between
-                // the two base pointers would otherwise go through a stack array)
-                const uint32_t b = min(b0 + row, B - 1);
-                const uint32_t n = min(n0 + (row < TB ? 0u : row - TB), c_o - 1);
-                const uintptr_t xa = reinterpret_cast<uintptr_t>(X + ((((size_t)b * Jtot + J) * L + l) * N + k));
-                const uintptr_t oa = reinterpret_cast<uintptr_t>(Op + ((((size_t)n * L + l) * Jtot + J) * N + k));
-                const uint32_t *src = reinterpret_cast<const uint32_t *>(row < TB ? xa : oa);
-                if (u < units) __builtin_amdgcn_global_load_lds(src, dst + u0 * 4u, 16, 0, 0);
-            }
-        }
-    };
-
-    uint64_t acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
-    uint32_t pc = 0;   // products in acc since the last fold (uniform)
-    const uint32_t off = g * GS;
-    // the rows this thread reads and their chunk permutations
-    uint32_t xrow[4], orow[4], xsw[4], osw[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const uint32_t rx = bi + TBq * u, ro = TB + ni + TNq * u;
-        xrow[u] = rx * R;
-        orow[u] = ro * R;
-        xsw[u] = (rx >> sw_shift) & (R4 - 1u);
-        osw[u] = (ro >> sw_shift) & (R4 - 1u);
-    }
-    issue(0, 0);
-    if (stages > 1) issue(1, 1);
-    for (uint32_t st = 0; st < stages; ++st) {
-        // this stage has landed once at most the next one's loads remain in flight
-        wait_loads_at_most(st + 1 < stages ? nld : 0u);
-        __builtin_amdgcn_s_barrier();
-        if (st + 2 < stages) issue(st + 2, (st + 2) % MD_BUFS);
-        const uint32_t *sb = lds + (st % MD_BUFS) * buf_words;
-        // unrolled by two, not fully: 120 registers instead of 146-162, one more wave per SIMD
-#pragma unroll 2
-        for (int k2 = 0; k2 < GS / 2; ++k2) {   // two slots per 8-byte read
-            const uint32_t k = off + 2u * k2;
-            const uint32_t ch = k >> 2, wd = k & 3u;
-            uint2 xv[4], ov[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                xv[u] = *reinterpret_cast<const uint2 *>(sb + xrow[u] + ((ch ^ xsw[u]) << 2) + wd);
-                ov[u] = *reinterpret_cast<const uint2 *>(sb + orow[u] + ((ch ^ osw[u]) << 2) + wd);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j] += (uint64_t)xv[i].x * ov[j].x;
-                    acc[i][j] += (uint64_t)xv[i].y * ov[j].y;
-                }
-            pc += 2;
-            if (pc >= 10) {
-                // hi 2^32 + lo == hi (2^32 mod q) + lo: below 2^62 + 2^32, and ten more
-                // products keep the sum below 2^64
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = (uint64_t)(uint32_t)(acc[i][j] >> 32) * c.r32 + (acc[i][j] & 0xffffffffull);
-                pc = 0;
-            }
-        }
-    }
-    uint32_t v[16];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[i * 4 + j] = reduce64(acc[i][j], c);
-    if (gpb > 1) {
-        // the gpb groups that share a block are consecutive; the first adds the others' sums
-        __syncthreads();   // every wave is done with the stage buffers
-        uint32_t *red = lds;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) red[tid * ML_RED_STRIDE + u] = v[u];
-        __syncthreads();
-        if (g % gpb == 0) {
-            for (uint32_t p = 1; p < gpb; ++p) {
-                const uint32_t *o = red + (tid + p * TBq * TNq) * ML_RED_STRIDE;
-#pragma unroll
-                for (int u = 0; u < 16; ++u) v[u] = addmod(v[u], o[u], c.q);
-            }
-        }
-    }
-    if (g % gpb != 0) return;
-    const uint32_t M = N >> s_log;
-    const uint32_t m = (base + off) >> s_log;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t b = b0 + bi + TBq * i, n = n0 + ni + TNq * j;
-            if (b < B && n < c_o) h[((size_t)(b * c_o + n) * L + l) * M + m] = v[i * 4 + j];
-        }
+    mac_dma_tile<GS, false>(X, Op, h, B, Jtot, Juse, c_o, L, N, s_log, gm, w, lds, lc);
 }
 
 __device__ __forceinline__ uint32_t mul_delta(uint32_t m, const LimbConst &c) {
@@ -641,6 +482,15 @@ hipError_t launch_mac_lds(const uint32_t *X, const uint32_t *Op, uint32_t *h, ui
     return hipGetLastError();
 }
 
+size_t mac_dma_lds_bytes(const MacLdsGeom &gm) {
+    // 16-byte chunks: R a power of two in [4, 64]; every slot of a stage within ML_UNITS loads per thread
+    if (gm.R < 4 || gm.R > 64 || (gm.R & (gm.R - 1)) || (4 * (gm.TBq + gm.TNq)) * (gm.R / 4) > ML_UNITS * ML_THREADS)
+        return SIZE_MAX;
+    const size_t stage = (size_t)MD_BUFS * 4 * (gm.TBq + gm.TNq) * gm.R;
+    const size_t red = (size_t)ML_THREADS * ML_RED_STRIDE;
+    return (stage > red ? stage : red) * sizeof(uint32_t);
+}
+
 hipError_t launch_mac_dma(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
                           uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool xcd_order,
                           const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
@@ -649,12 +499,8 @@ hipError_t launch_mac_dma(const uint32_t *X, const uint32_t *Op, uint32_t *h, ui
     size_t lds_pad = 0;
     // without register staging, blocks shorter than 16 slots take 64-slot stages (x4 MAC 10.3 -> 9.4 ms)
     if (Juse == 0 || !mac_lds_geometry(B, c_o, N, s, &gm, &lds_pad, 64)) return hipErrorInvalidValue;
-    // 16-byte chunks: R a power of two in [4, 64]; every slot of a stage within ML_UNITS loads per thread
-    if (gm.R < 4 || gm.R > 64 || (gm.R & (gm.R - 1)) || (4 * (gm.TBq + gm.TNq)) * (gm.R / 4) > ML_UNITS * ML_THREADS)
-        return hipErrorInvalidValue;
-    const size_t stage = (size_t)MD_BUFS * 4 * (gm.TBq + gm.TNq) * gm.R;
-    const size_t red = (size_t)ML_THREADS * ML_RED_STRIDE;
-    const size_t lds = (stage > red ? stage : red) * sizeof(uint32_t);
+    const size_t lds = mac_dma_lds_bytes(gm);
+    if (lds == SIZE_MAX) return hipErrorInvalidValue;
     uint32_t s_log = 0;
     while ((1u << s_log) < s) ++s_log;
     const uint32_t tiles = L * gm.ranges * gm.tiles_b * gm.tiles_n;
