@@ -39,9 +39,9 @@ CUS, CLOCK_GHZ = 256, 2.4
 # on an MI355X, the figures of profiles/alu_rates_MI355X.md; a run replaces them with its own
 # measurement unless --no-rates.  A Shoup butterfly is 9 vector instructions (1 mul_hi, 2 mul_lo,
 # 6 add / sub / min); the MAC's inner product is one v_mad_u64_u32 per product.
-BFLY_PEAK_G = 4005.8
-GSBFLY_PEAK_G = 4254.0
-MAD64_PEAK_G = 33005.4
+BFLY_PEAK_G = 4084.5
+GSBFLY_PEAK_G = 4368.0
+MAD64_PEAK_G = 32825.4
 
 
 def alu_rates(he):
@@ -60,43 +60,44 @@ PMC_TRAFFIC = {
     # the launch that carries each layer's MAC, per layer of the stack with every layer pinned to each
     # form in turn: k_mac_tail (F, fused MAC and inverse), k_mac_class / k_mac_full (S, split), and
     # the whole layer in one launch, k_fused_layer (O) or k_fused_rows (R; the FC head runs O).  Each
-    # form is valid while the sources of its kernels are the ones that were measured.
+    # form is valid while the sources of its kernels are the ones that were measured
+    # (profiles/pmc_traffic_plain20_x1_N8192_L4_per_layer.md).
     "layers": {
         "forms": {
             "F": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "619acfff01cfa3e3e18ee784bf8138d685ebe74da9abf6577da2bcae7f1f0906"},
-            "S": {"sources": ['paper_2409_05205_amd/csrc/kernels_mac.hip', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "7329e4bdb82b34969facab387754bd2b365ffb488c53661c206685bed351d260"},
-            "O": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "7c09984a20f76ed5ee118323bffebc5ed6292e998621b503b72299cb17594d2c"},
-            "R": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": ""},
+                  "sha256": "1ad4e747fc0daf9ca6d0705f8b203b15035e47c18c9c838ec398ef1ad9613f29"},
+            "S": {"sources": ['paper_2409_05205_amd/csrc/kernels_mac.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
+                  "sha256": "e8d4cad067275e3a1e538687fbfb28cd4de9eac1d683b2964a110b049ad357f6"},
+            "O": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
+                  "sha256": "e6ac9c3c7773665a2f8989aa943dd7f3091e237cb6a659c1531e32005a67d655"},
+            "R": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
+                  "sha256": "e6ac9c3c7773665a2f8989aa943dd7f3091e237cb6a659c1531e32005a67d655"},
         },
         "per_layer": [
-            {"F": 4729651, "S": 2794341, "O": 8134309, "R": None},
-            {"F": 21239768, "S": 18388963, "O": 27282265, "R": None},
-            {"F": 21239786, "S": 18388963, "O": 27281204, "R": None},
-            {"F": 21239860, "S": 18389036, "O": 27273763, "R": None},
-            {"F": 21239695, "S": 18388963, "O": 27277292, "R": None},
-            {"F": 21240061, "S": 18388963, "O": 27282448, "R": None},
-            {"F": 21239860, "S": 18388963, "O": 27283892, "R": None},
-            {"F": 40111397, "S": 35688562, "O": 48275817, "R": None},
-            {"F": 19040913, "S": 17602779, "O": 22390790, "R": None},
-            {"F": 19040767, "S": 17602596, "O": 22390735, "R": None},
-            {"F": 19040986, "S": 17602742, "O": 22392728, "R": None},
-            {"F": 19040694, "S": 17602596, "O": 22391869, "R": None},
-            {"F": 19040895, "S": 17602596, "O": 22391869, "R": None},
-            {"F": 36864052, "S": 34641103, "O": 41295020, "R": None},
-            {"F": 17950471, "S": 17209413, "O": 19837153, "R": None},
-            {"F": 17950380, "S": 17209413, "O": 19839566, "R": None},
-            {"F": 17950490, "S": 17209413, "O": 19839310, "R": None},
-            {"F": 17950581, "S": 17209559, "O": 19838469, "R": None},
-            {"F": 17950234, "S": 17209267, "O": 19837975, "R": None},
-            {"F": None, "S": 704441, "O": 2245792, "R": None},
+            {"F": 4729513, "S": 2793493, "O": 8153008, "R": 5407888},
+            {"F": 21239908, "S": 18389341, "O": 27323289, "R": 24133970},
+            {"F": 21239871, "S": 18389048, "O": 27322704, "R": 24132398},
+            {"F": 21239871, "S": 18389048, "O": 27320071, "R": 24132672},
+            {"F": 21239816, "S": 18389048, "O": 27318809, "R": 24132050},
+            {"F": 21240109, "S": 18389066, "O": 27323599, "R": 24132745},
+            {"F": 21239889, "S": 18389048, "O": 27317822, "R": 24131739},
+            {"F": 40111469, "S": 35688800, "O": 48312234, "R": 43018147},
+            {"F": 19041012, "S": 17602843, "O": 22426679, "R": 20847751},
+            {"F": 19040866, "S": 17602679, "O": 22428123, "R": 20847842},
+            {"F": 19041030, "S": 17602825, "O": 22428434, "R": 20847861},
+            {"F": 19040847, "S": 17602679, "O": 22429019, "R": 20847623},
+            {"F": 19040975, "S": 17602679, "O": 22428818, "R": 20847769},
+            {"F": 36864137, "S": 34640863, "O": 41319978, "R": 38844383},
+            {"F": 17950495, "S": 17209494, "O": 19870611, "R": 19254190},
+            {"F": 17950440, "S": 17209494, "O": 19873884, "R": 19287338},
+            {"F": 17950386, "S": 17209494, "O": 19874085, "R": 19272217},
+            {"F": 17950642, "S": 17209641, "O": 19874268, "R": 19277867},
+            {"F": 17950148, "S": 17209348, "O": 19872769, "R": 19258249},
+            {"F": None, "S": 704443, "O": 2245315, "R": 2245190},
         ]},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h'],
                 "sha256": "49292b8e7dd98223913862ab1c3c1ae2c3e9afcbc77088f7fd93d3c857110c67",
-                "bytes_per_launch": 2833849},
+                "bytes_per_launch": 2834223},
 }
 
 
