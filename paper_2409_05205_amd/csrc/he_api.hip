@@ -1626,9 +1626,12 @@ int he_group_create(const he_layer_call *calls, uint32_t n, uint32_t flags, he_g
     g->jobs.resize(n);
     for (uint32_t i = 0; i < n; ++i) {
         const he_layer_call &c = calls[i];
-        if (!c.ctx || c.ctx->device != g->device || !c.layer || c.layer->ctx != c.ctx || c.B == 0) return HE_EINVAL;
-        const int rc = check_layer_args(c.ctx, c.layer, c.layer->info.kind, c.d_c0, c.d_out, c.d_c0);
-        if (rc != HE_OK) return rc;
+        // the buffers of a layer call (the workspace is the group's own)
+        if (!c.ctx || c.ctx->device != g->device || !c.layer || c.layer->ctx != c.ctx || c.B == 0 || !c.d_c0 ||
+            !c.d_out || !aligned16(c.d_c0) || (c.layer->info.kind == HE_LAYER_CONV && !aligned16(c.d_out))) {
+            g_last_error = "he_group_create: call " + std::to_string(i) + ": invalid arguments";
+            return HE_EINVAL;
+        }
         FusedLayer jb;
         if (!fused_layer_shape(c.ctx, c.layer, c.B, false, jb)) {
             g_last_error = "he_group_create: call " + std::to_string(i) +

@@ -522,9 +522,9 @@ __device__ __forceinline__ void fz_tail_switch(const FusedLayer &jb, uint32_t it
     }
 }
 
-// Tails in the grouped launch: 128 threads per vector from 512 points up (two or more vectors per
-// item, as the batched tail kernel takes them), twiddles read per pass (registers go to occupancy).
-constexpr int fz_group_tail_logr(int logm) { return logm >= 9 ? logm - 7 : 2; }
+// Tails in the grouped launch: 64 threads per vector from 256 points up (four or more vectors per
+// item; 128 threads at 4096 points), twiddles read per pass (registers go to occupancy).
+constexpr int fz_group_tail_logr(int logm) { return logm >= 8 ? (logm - 6 < 5 ? logm - 6 : 5) : 2; }
 
 __device__ __forceinline__ void fz_tail_switch_group(const FusedLayer &jb, uint32_t it, uint32_t *lds,
                                                      const uint32_t *twi, const uint32_t *twish, const LimbConsts &lc,

@@ -216,3 +216,35 @@ def test_group_rejects_full_intt_layers(he):
     with pytest.raises(he.HEError) as e:
         grp.build()
     assert e.value.code == he.HE_EUNSUPPORTED
+
+
+def test_group_rejects_invalid_calls(he):
+    """Invalid calls are refused at creation with HE_EINVAL before anything runs: a layer of
+    another context, a batch of zero, a missing output, an unknown MAC flag."""
+    ctx_a, ctx_b = he.Context(4096, 2, T), he.Context(4096, 2, T)
+    rng = np.random.default_rng(9)
+    spec = he.ConvSpec(3, 8, 8, 8, 3, 1, 1)
+    i = ctx_a.geometry(spec)
+    layer = ctx_a.pack_conv(spec, rng.integers(-7, 8, (8, 3, 3, 3)), rng.integers(0, T, (i.K_in, 8, 4096)))
+    c0 = dev(np.stack([wl.uniform_per_modulus(rng, (i.K_in,), ctx_a.primes, 4096)]))
+    out = dev(np.zeros((1, i.K_out, 2, 4096), dtype=np.int64))
+    lib = he.load_library()
+    import ctypes
+
+    def create(calls, flags=0):
+        arr = (he.LayerCall * len(calls))(*calls)
+        h = ctypes.c_void_p()
+        rc = lib.he_group_create(arr, len(calls), flags, ctypes.byref(h))
+        if rc == he.HE_OK:
+            lib.he_group_free(h)
+        return rc
+
+    good = he.LayerCall(ctx_a.handle, layer.handle, 1, c0.data_ptr(), None, None, out.data_ptr())
+    assert create([good]) == he.HE_OK
+    assert create([he.LayerCall(ctx_b.handle, layer.handle, 1, c0.data_ptr(), None, None, out.data_ptr())]) == \
+        he.HE_EINVAL
+    assert create([he.LayerCall(ctx_a.handle, layer.handle, 0, c0.data_ptr(), None, None, out.data_ptr())]) == \
+        he.HE_EINVAL
+    assert create([he.LayerCall(ctx_a.handle, layer.handle, 1, c0.data_ptr(), None, None, None)]) == he.HE_EINVAL
+    assert create([good], flags=7) == he.HE_EINVAL
+    assert lib.he_group_create(None, 0, 0, ctypes.byref(ctypes.c_void_p())) == he.HE_EINVAL
