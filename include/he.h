@@ -366,9 +366,10 @@ void he_seq_free(he_seq *seq);
  * HE_GROUP_MAC_AUTO (image tiles for conv calls of B >= 4), HE_GROUP_MAC_PER_IMAGE
  * (one image per MAC item), HE_GROUP_MAC_TILED (image tiles wherever the shape
  * allows).  *out = NULL on failure.
- * he_group_run -- one launch on `stream`; allocates nothing (it may be
- * captured into a HIP graph).  The counters return to zero by the end of each
- * launch; launches of one group must not overlap (one stream at a time).
+ * he_group_run -- one launch on `stream`, with the group's device current (as
+ * for every layer call); allocates nothing (it may be captured into a HIP
+ * graph).  The counters return to zero by the end of each launch; launches of
+ * one group must not overlap (one stream at a time).
  * he_group_check -- synchronises the stream; HE_EDEVICE if an item of an earlier
  * launch gave up waiting (about a second; its call's words are then undefined;
  * the flag is cleared), else HE_OK.
