@@ -69,31 +69,31 @@ PMC_TRAFFIC = {
             "S": {"sources": ['paper_2409_05205_amd/csrc/kernels_mac.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
                   "sha256": "e8d4cad067275e3a1e538687fbfb28cd4de9eac1d683b2964a110b049ad357f6"},
             "O": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "e6ac9c3c7773665a2f8989aa943dd7f3091e237cb6a659c1531e32005a67d655"},
+                  "sha256": "a7d023c8c6d56cd269cde56570926d592eacc89e2a37f625d10d5cbdd3f1a5ff"},
             "R": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "e6ac9c3c7773665a2f8989aa943dd7f3091e237cb6a659c1531e32005a67d655"},
+                  "sha256": "a7d023c8c6d56cd269cde56570926d592eacc89e2a37f625d10d5cbdd3f1a5ff"},
         },
         "per_layer": [
-            {"F": 4729513, "S": 2793493, "O": 8153008, "R": 5407888},
-            {"F": 21239908, "S": 18389341, "O": 27323289, "R": 24133970},
-            {"F": 21239871, "S": 18389048, "O": 27322704, "R": 24132398},
-            {"F": 21239871, "S": 18389048, "O": 27320071, "R": 24132672},
-            {"F": 21239816, "S": 18389048, "O": 27318809, "R": 24132050},
-            {"F": 21240109, "S": 18389066, "O": 27323599, "R": 24132745},
-            {"F": 21239889, "S": 18389048, "O": 27317822, "R": 24131739},
-            {"F": 40111469, "S": 35688800, "O": 48312234, "R": 43018147},
-            {"F": 19041012, "S": 17602843, "O": 22426679, "R": 20847751},
-            {"F": 19040866, "S": 17602679, "O": 22428123, "R": 20847842},
-            {"F": 19041030, "S": 17602825, "O": 22428434, "R": 20847861},
-            {"F": 19040847, "S": 17602679, "O": 22429019, "R": 20847623},
-            {"F": 19040975, "S": 17602679, "O": 22428818, "R": 20847769},
-            {"F": 36864137, "S": 34640863, "O": 41319978, "R": 38844383},
-            {"F": 17950495, "S": 17209494, "O": 19870611, "R": 19254190},
-            {"F": 17950440, "S": 17209494, "O": 19873884, "R": 19287338},
-            {"F": 17950386, "S": 17209494, "O": 19874085, "R": 19272217},
-            {"F": 17950642, "S": 17209641, "O": 19874268, "R": 19277867},
-            {"F": 17950148, "S": 17209348, "O": 19872769, "R": 19258249},
-            {"F": None, "S": 704443, "O": 2245315, "R": 2245190},
+            {"F": 4729513, "S": 2793493, "O": 8170044, "R": 5412404},
+            {"F": 21239908, "S": 18389341, "O": 27302986, "R": 24146622},
+            {"F": 21239871, "S": 18389048, "O": 27299750, "R": 24147811},
+            {"F": 21239871, "S": 18389048, "O": 27297355, "R": 24146458},
+            {"F": 21239816, "S": 18389048, "O": 27300262, "R": 24146330},
+            {"F": 21240109, "S": 18389066, "O": 27302510, "R": 24146037},
+            {"F": 21239889, "S": 18389048, "O": 27303041, "R": 24145818},
+            {"F": 40111469, "S": 35688800, "O": 48294659, "R": 43045645},
+            {"F": 19041012, "S": 17602843, "O": 22428613, "R": 20820472},
+            {"F": 19040866, "S": 17602679, "O": 22431410, "R": 20820636},
+            {"F": 19041030, "S": 17602825, "O": 22433165, "R": 20820856},
+            {"F": 19040847, "S": 17602679, "O": 22432379, "R": 20820710},
+            {"F": 19040975, "S": 17602679, "O": 22432324, "R": 20820600},
+            {"F": 36864137, "S": 34640863, "O": 41330337, "R": 38813722},
+            {"F": 17950495, "S": 17209494, "O": 19848294, "R": 19264502},
+            {"F": 17950440, "S": 17209494, "O": 19847947, "R": 19260022},
+            {"F": 17950386, "S": 17209494, "O": 19852919, "R": 19259894},
+            {"F": 17950642, "S": 17209641, "O": 19848696, "R": 19260388},
+            {"F": 17950148, "S": 17209348, "O": 19850707, "R": 19260077},
+            {"F": None, "S": 704443, "O": 2251190, "R": 2253509},
         ]},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h'],
                 "sha256": "49292b8e7dd98223913862ab1c3c1ae2c3e9afcbc77088f7fd93d3c857110c67",
