@@ -248,3 +248,44 @@ def test_group_rejects_invalid_calls(he):
     assert create([he.LayerCall(ctx_a.handle, layer.handle, 1, c0.data_ptr(), None, None, None)]) == he.HE_EINVAL
     assert create([good], flags=7) == he.HE_EINVAL
     assert lib.he_group_create(None, 0, 0, ctypes.byref(ctypes.c_void_p())) == he.HE_EINVAL
+
+
+def test_group_graph_replays(he):
+    """A grouped launch captured into a HIP graph: every replay, with eager work between the
+    replays, gives the words of the eager launch (the counters return to zero inside the launch,
+    so the graph needs no memset node)."""
+    import torch
+    ctxs = {"a": he.Context(4096, 3, T), "b": he.Context(8192, 2, T)}
+    octxs = {k: bfv.make_ctx(c.N, c.L, T) for k, c in ctxs.items()}
+    grp = he.Group()
+    outs, wants = [], []
+    for i, case in enumerate(SMALL):
+        args, want = _small_case(he, ctxs, octxs, i, *case)
+        outs.append(grp.add(*args))
+        wants.append(want)
+    grp.build()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        grp.run(stream)            # eager launch first (nothing is allocated during capture either way)
+    stream.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        grp.run(stream)
+    stream.synchronize()
+    other_args, other_want = _small_case(he, ctxs, octxs, 99, "a", "conv", (16, 16, 16, 1, 3, 1), 2, False, False)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        # eager work between the replays
+        other = host(ctxs["a"].conv_layer(*other_args))
+        for b, w in enumerate(other_want):
+            assert (other[b] == w).all()
+        for i, (o, want) in enumerate(zip(outs, wants)):
+            got = host(o)
+            for b, w in enumerate(want):
+                assert (got[b] == w).all(), f"replay {rep} call {i} image {b}"
+    grp.check(stream)
+    grp.free()
