@@ -266,15 +266,14 @@ __device__ __forceinline__ void mac_dma_tile(const uint32_t *__restrict__ X, con
         for (int j = 0; j < 4; ++j) acc[i][j] = 0;
     uint32_t pc = 0;   // products in acc since the last fold (uniform)
     const uint32_t off = g * GS;
-    // the rows this thread reads and their chunk permutations
-    uint32_t xrow[4], orow[4], xsw[4], osw[4];
+    // row r's word at column 4 ch + wd sits at r R + ((ch ^ sw(r)) << 2) + wd; with R a power of two
+    // and (ch ^ sw) << 2 below R this is (r R | sw(r) << 2) ^ (ch << 2), plus wd: one register per row
+    uint32_t xb[4], ob[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const uint32_t rx = bi + TBq * u, ro = TB + ni + TNq * u;
-        xrow[u] = rx * R;
-        orow[u] = ro * R;
-        xsw[u] = (rx >> sw_shift) & (R4 - 1u);
-        osw[u] = (ro >> sw_shift) & (R4 - 1u);
+        xb[u] = rx * R | (((rx >> sw_shift) & (R4 - 1u)) << 2);
+        ob[u] = ro * R | (((ro >> sw_shift) & (R4 - 1u)) << 2);
     }
     issue(0, 0);
     if (stages > 1) issue(1, 1);
@@ -292,8 +291,8 @@ __device__ __forceinline__ void mac_dma_tile(const uint32_t *__restrict__ X, con
             uint2 xv[4], ov[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                xv[u] = *reinterpret_cast<const uint2 *>(sb + xrow[u] + ((ch ^ xsw[u]) << 2) + wd);
-                ov[u] = *reinterpret_cast<const uint2 *>(sb + orow[u] + ((ch ^ osw[u]) << 2) + wd);
+                xv[u] = *reinterpret_cast<const uint2 *>(sb + (xb[u] ^ (ch << 2)) + wd);
+                ov[u] = *reinterpret_cast<const uint2 *>(sb + (ob[u] ^ (ch << 2)) + wd);
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
