@@ -67,33 +67,33 @@ PMC_TRAFFIC = {
             "F": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
                   "sha256": "1ad4e747fc0daf9ca6d0705f8b203b15035e47c18c9c838ec398ef1ad9613f29"},
             "S": {"sources": ['paper_2409_05205_amd/csrc/kernels_mac.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "e8d4cad067275e3a1e538687fbfb28cd4de9eac1d683b2964a110b049ad357f6"},
+                  "sha256": "9979c72f0e5bd3f8d074c26d9a20ff0e9f2023704aba631fe05efecaf90ecfe7"},
             "O": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "a7d023c8c6d56cd269cde56570926d592eacc89e2a37f625d10d5cbdd3f1a5ff"},
+                  "sha256": "3fa3dc15a11e9bff84a373a56ef09389b6c319e7d90280a9f7a5725e1d38aee3"},
             "R": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "a7d023c8c6d56cd269cde56570926d592eacc89e2a37f625d10d5cbdd3f1a5ff"},
+                  "sha256": "3fa3dc15a11e9bff84a373a56ef09389b6c319e7d90280a9f7a5725e1d38aee3"},
         },
         "per_layer": [
-            {"F": 4729513, "S": 2793493, "O": 8170044, "R": 5412404},
-            {"F": 21239908, "S": 18389341, "O": 27302986, "R": 24146622},
-            {"F": 21239871, "S": 18389048, "O": 27299750, "R": 24147811},
-            {"F": 21239871, "S": 18389048, "O": 27297355, "R": 24146458},
-            {"F": 21239816, "S": 18389048, "O": 27300262, "R": 24146330},
-            {"F": 21240109, "S": 18389066, "O": 27302510, "R": 24146037},
-            {"F": 21239889, "S": 18389048, "O": 27303041, "R": 24145818},
-            {"F": 40111469, "S": 35688800, "O": 48294659, "R": 43045645},
-            {"F": 19041012, "S": 17602843, "O": 22428613, "R": 20820472},
-            {"F": 19040866, "S": 17602679, "O": 22431410, "R": 20820636},
-            {"F": 19041030, "S": 17602825, "O": 22433165, "R": 20820856},
-            {"F": 19040847, "S": 17602679, "O": 22432379, "R": 20820710},
-            {"F": 19040975, "S": 17602679, "O": 22432324, "R": 20820600},
-            {"F": 36864137, "S": 34640863, "O": 41330337, "R": 38813722},
-            {"F": 17950495, "S": 17209494, "O": 19848294, "R": 19264502},
-            {"F": 17950440, "S": 17209494, "O": 19847947, "R": 19260022},
-            {"F": 17950386, "S": 17209494, "O": 19852919, "R": 19259894},
-            {"F": 17950642, "S": 17209641, "O": 19848696, "R": 19260388},
-            {"F": 17950148, "S": 17209348, "O": 19850707, "R": 19260077},
-            {"F": None, "S": 704443, "O": 2251190, "R": 2253509},
+            {"F": 4729513, "S": 2793489, "O": 8169392, "R": 5412203},
+            {"F": 21239908, "S": 18389307, "O": 27300482, "R": 24147335},
+            {"F": 21239871, "S": 18389014, "O": 27303261, "R": 24146238},
+            {"F": 21239871, "S": 18389014, "O": 27300628, "R": 24146257},
+            {"F": 21239816, "S": 18389014, "O": 27299659, "R": 24146183},
+            {"F": 21240109, "S": 18389051, "O": 27299641, "R": 24146823},
+            {"F": 21239889, "S": 18389014, "O": 27301176, "R": 24146238},
+            {"F": 40111469, "S": 35688734, "O": 48296852, "R": 43045682},
+            {"F": 19041012, "S": 17602865, "O": 22430549, "R": 20821057},
+            {"F": 19040866, "S": 17602646, "O": 22433328, "R": 20820801},
+            {"F": 19041030, "S": 17602792, "O": 22433493, "R": 20820929},
+            {"F": 19040847, "S": 17602646, "O": 22432268, "R": 20820947},
+            {"F": 19040975, "S": 17602646, "O": 22432396, "R": 20820929},
+            {"F": 36864137, "S": 34641246, "O": 41334044, "R": 38816318},
+            {"F": 17950495, "S": 17209462, "O": 19852529, "R": 19245560},
+            {"F": 17950440, "S": 17209462, "O": 19853023, "R": 19276496},
+            {"F": 17950386, "S": 17209462, "O": 19851249, "R": 19262765},
+            {"F": 17950642, "S": 17209608, "O": 19848397, "R": 19266934},
+            {"F": 17950148, "S": 17209315, "O": 19851981, "R": 19249308},
+            {"F": None, "S": 704442, "O": 2252190, "R": 2253363},
         ]},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h'],
                 "sha256": "49292b8e7dd98223913862ab1c3c1ae2c3e9afcbc77088f7fd93d3c857110c67",

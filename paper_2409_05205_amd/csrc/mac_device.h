@@ -283,7 +283,7 @@ __device__ __forceinline__ void mac_dma_tile(const uint32_t *__restrict__ X, con
         __builtin_amdgcn_s_barrier();
         if (st + 2 < stages) issue(st + 2, (st + 2) % MD_BUFS);
         const uint32_t *sb = lds + (st % MD_BUFS) * buf_words;
-        // unrolled by two, not fully: 120 registers instead of 146-162, one more wave per SIMD
+        // unrolled by two, not fully: 102 registers instead of 146-162, one more wave per SIMD
 #pragma unroll 2
         for (int k2 = 0; k2 < GS / 2; ++k2) {   // two slots per 8-byte read
             const uint32_t k = off + 2u * k2;
