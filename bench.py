@@ -42,6 +42,8 @@ CUS, CLOCK_GHZ = 256, 2.4
 BFLY_PEAK_G = 4084.5
 GSBFLY_PEAK_G = 4368.0
 MAD64_PEAK_G = 32825.4
+# the matrix cores' published dense int8 rate (T operations per second, 2 per multiply-add)
+INT8_PEAK_T = 5000.0
 
 
 def alu_rates(he):
@@ -199,11 +201,11 @@ class Stack:
     def mac_plan(self, he):
         """Which launch carries each layer's MAC: 'one' / 'rows' (the whole layer in one launch:
         work items of sub-blocks, chunks and tails / one MAC + inverse item per output row), 'fused'
-        (MAC + residue-class tail in one launch, after a forward-transform launch) or 'split' (MAC
-        launch, then tail / inverse launch), read from the kernel kinds one call of the layer
-        records."""
+        (MAC + residue-class tail in one launch, after a forward-transform launch), 'split' (MAC
+        launch, then tail / inverse launch) or 'mfma' (the same with the MAC on the matrix cores),
+        read from the kernel kinds one call of the layer records."""
         plan = []
-        kinds = he.HE_K_MAC | he.HE_K_MAC_TAIL | he.HE_K_LAYER | he.HE_K_LAYER_ROWS
+        kinds = he.HE_K_MAC | he.HE_K_MAC_TAIL | he.HE_K_LAYER | he.HE_K_LAYER_ROWS | he.HE_K_MAC_MFMA
         for ly, B, c0, sh, shn in self.steps:
             self.ctx.profile_reset()
             self.ctx.profile_enable(kinds)
@@ -214,8 +216,9 @@ class Stack:
             one = self.ctx.profile_read(he.HE_K_LAYER)[0] > 0
             rows = self.ctx.profile_read(he.HE_K_LAYER_ROWS)[0] > 0
             fused = self.ctx.profile_read(he.HE_K_MAC_TAIL)[0] > 0
+            mfma = self.ctx.profile_read(he.HE_K_MAC_MFMA)[0] > 0
             self.ctx.profile_enable(0)
-            plan.append("one" if one else ("rows" if rows else ("fused" if fused else "split")))
+            plan.append("one" if one else ("rows" if rows else ("fused" if fused else ("mfma" if mfma else "split"))))
         self.ctx.profile_reset()
         return plan
 
@@ -352,7 +355,8 @@ def batched_rooflines(he, ctx, st, stream, sync, passes=2, plan=None):
     tuner put in a one-launch form (`plan`) are reported apart, against HBM."""
     import torch
     kinds = [("ntt_fwd", he.HE_K_NTT_FWD), ("mac", he.HE_K_MAC), ("tail", he.HE_K_TAIL), ("intt", he.HE_K_INTT),
-             ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER), ("layer_rows", he.HE_K_LAYER_ROWS)]
+             ("mac_tail", he.HE_K_MAC_TAIL), ("layer", he.HE_K_LAYER), ("layer_rows", he.HE_K_LAYER_ROWS),
+             ("mac_mfma", he.HE_K_MAC_MFMA)]
     ctx.profile_reset()
     ctx.profile_enable(sum(k for _, k in kinds))
     with torch.cuda.stream(stream):
@@ -368,6 +372,8 @@ def batched_rooflines(he, ctx, st, stream, sync, passes=2, plan=None):
     out = {}
     one = [p in ("one", "rows") for p in plan] if plan is not None else [False] * len(st.steps)
     multi = [not o for o in one]
+    on_mfma = [p == "mfma" for p in plan] if plan is not None else [False] * len(st.steps)
+    valu_mac = [m and not f for m, f in zip(multi, on_mfma)]
 
     def hbm(nbytes, t_ms):
         gbs = nbytes / (t_ms / 1e3) / 1e9
@@ -380,11 +386,20 @@ def batched_rooflines(he, ctx, st, stream, sync, passes=2, plan=None):
                           **hbm(st.fwd_bytes(multi), ms["ntt_fwd"])}
     mac_ms = ms["mac"] + ms["mac_tail"]
     if mac_ms:
-        mac_rate = st.modmuls(multi) / (mac_ms / 1e3) / 1e9
+        mac_rate = st.modmuls(valu_mac) / (mac_ms / 1e3) / 1e9
         out["mac"] = {"ms_per_batch": round(mac_ms, 3), "bound": "alu", "achieved": round(mac_rate, 1),
-                      "peak": MAD64_PEAK_G, "unit": "Gmodmul/s", "frac": round(mac_rate / MAD64_PEAK_G, 4)}
+                      "peak": MAD64_PEAK_G, "unit": "Gmodmul/s", "frac": round(mac_rate / MAD64_PEAK_G, 4),
+                      "layers": sum(valu_mac)}
         if plan is not None:
-            out["mac"].update(hbm(st.mac_kernel_bytes(plan, only=multi), mac_ms))
+            out["mac"].update(hbm(st.mac_kernel_bytes(plan, only=valu_mac), mac_ms))
+    if ms["mac_mfma"]:
+        # each modular product is 16 products of 8-bit digits (2 int8 ops each) on the matrix cores
+        mm = st.modmuls(on_mfma)
+        tops = 32 * mm / (ms["mac_mfma"] / 1e3) / 1e12
+        out["mac_mfma"] = {"ms_per_batch": round(ms["mac_mfma"], 3), "bound": "mfma", "achieved": round(tops, 1),
+                           "peak": INT8_PEAK_T, "unit": "TOP/s (int8)", "frac": round(tops / INT8_PEAK_T, 4),
+                           "Gmodmul_per_s": round(mm / (ms["mac_mfma"] / 1e3) / 1e9, 1), "layers": sum(on_mfma),
+                           **hbm(st.mac_kernel_bytes(plan, only=on_mfma), ms["mac_mfma"])}
     inv_ms = ms["tail"] + ms["intt"]
     if inv_ms:
         inv_rate = st.tail_butterflies(multi) / (inv_ms / 1e3) / 1e9
@@ -833,7 +848,7 @@ def main():
     log(f"plain: {T_plain / args.steps * 1e3:.3f} ms/step")
     if args.pmc_mac_form is not None:
         # layer order of the MAC launches above is the stack order, one per layer per call
-        plan = "".join({"one": "O", "rows": "R", "fused": "F", "split": "S"}[p] for p in st.mac_plan(he))
+        plan = "".join({"one": "O", "rows": "R", "fused": "F", "split": "S", "mfma": "M"}[p] for p in st.mac_plan(he))
         print(json.dumps({"pmc_mac_form": args.pmc_mac_form, "plan": plan,
                           "calls": args.warmup + args.steps + 1}), flush=True)
         return
@@ -892,7 +907,7 @@ def main():
     # split MAC (FC head, and any layer the tuner gave the two-launch form)
     rooflines = {}
     per_step = {}
-    plan_letters = "".join({"one": "O", "rows": "R", "fused": "F", "split": "S"}[p] for p in plan)
+    plan_letters = "".join({"one": "O", "rows": "R", "fused": "F", "split": "S", "mfma": "M"}[p] for p in plan)
     one_sel = [p in ("one", "rows") for p in plan]
     n_one = sum(one_sel)
     lay_n = kern["layer"]["launches"] + kern["layer_rows"]["launches"]

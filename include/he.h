@@ -272,10 +272,11 @@ int he_poly_mul(he_ctx *ctx, uint32_t rows, const uint32_t *d_a, const uint32_t 
  * HE_K_LAYER (the whole layer in one launch: forward transforms, MAC, inverse
  * and extraction), HE_K_LAYER_ROWS (the same with one MAC + inverse item per
  * output row), HE_K_GROUP (a grouped launch, he_group_run; recorded on the
- * context of the group's first call).
+ * context of the group's first call), HE_K_MAC_MFMA (the batched MAC on the
+ * matrix cores, HE_TUNE_MAC = 9).
  */
 enum { HE_K_NTT_FWD = 1, HE_K_MAC = 2, HE_K_TAIL = 4, HE_K_INTT = 8, HE_K_MAC_TAIL = 16, HE_K_LAYER = 32,
-       HE_K_LAYER_ROWS = 64, HE_K_GROUP = 128 };
+       HE_K_LAYER_ROWS = 64, HE_K_GROUP = 128, HE_K_MAC_MFMA = 256 };
 int he_profile_enable(he_ctx *ctx, uint32_t kind_mask);
 int he_profile_read(he_ctx *ctx, uint32_t kind, uint64_t *launches, double *total_ms);
 int he_profile_reset(he_ctx *ctx);
@@ -456,7 +457,9 @@ void he_server_free(he_server *srv);
  * moved from memory to LDS by DMA, three stages in flight), 7 (conv and FC:
  * the whole layer in one launch, forward transforms included, work items in
  * workgroup order that wait on counters), 8 (conv: one launch of whole-row
- * transforms and one MAC + inverse item per output row) or -1 (automatic:
+ * transforms and one MAC + inverse item per output row), 9 (residue-class conv
+ * layers, s >= 4: the batched MAC on the integer matrix cores, residues split
+ * into signed 8-bit digits whose products are summed exactly) or -1 (automatic:
  * 7 for FC layers at B = 1 where the shape allows it (N 4096..16384,
  * n_o' <= 1024); for conv layers at B = 1, 2, except 0 for layers with
  * K_in >= 2 and at most 64 output rows K_out g_o L; at B >= 4, 5 for

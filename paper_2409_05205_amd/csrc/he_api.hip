@@ -279,6 +279,13 @@ bool mac_lds_ok(const he_layer *ly, uint32_t B) {
     return B >= 2 && in.kind == HE_LAYER_CONV && in.flags == HE_PACK_CLASS_INTT && in.s >= 2 && in.N >= 256;
 }
 
+// the matrix-core batched MAC: residue-class conv layers with s >= 4, every input row's K = s
+// slots per block (the sum over rows of one block at most 32768 products)
+bool mac_mfma_layer_ok(const he_layer *ly, uint32_t B) {
+    const he_layer_info &in = ly->info;
+    return mac_lds_ok(ly, B) && mac_mfma_ok(B, 2 * in.K_in, in.N, in.s);
+}
+
 // The item geometry of this layer at batch B in the one-launch / grouped forms (kernels_fused.hip),
 // before the plan, in f; false when the shape is outside them.
 bool fused_layer_shape(const he_ctx *ctx, const he_layer *ly, uint32_t B, bool rows, FusedLayer &f) {
@@ -319,6 +326,7 @@ bool layer_one_launch_ok(const he_ctx *ctx, const he_layer *ly, uint32_t B, Fuse
 int mac_variant_multi(he_ctx *ctx, const he_layer *ly, uint32_t B, int mk) {
     const bool tiled_ok = mac_tiled_ok(ly, B), fused_ok = mac_fused_ok(ctx, ly);
     if (mk == 3 || mk == 4 || mk == 5 || mk == 6) return mac_lds_ok(ly, B) ? mk : 0;
+    if (mk == 9) return mac_mfma_layer_ok(ly, B) ? 9 : 0;
     if (mk == 2) return fused_ok ? 2 : 0;
     if (mk == 1) return tiled_ok ? 1 : 0;
     if (mk == 0) return 0;
@@ -346,7 +354,7 @@ int mac_variant(he_ctx *ctx, const he_layer *ly, uint32_t B) {
     if (mk == 8 && layer_one_launch_ok(ctx, ly, B, nullptr, true)) return 8;
     if ((mk == 7 || mk == 8 || (mk < 0 && B == 1 && !conv)) && layer_one_launch_ok(ctx, ly, B, nullptr)) return 7;
     if (!conv) return -1;
-    return mac_variant_multi(ctx, ly, B, mk >= 7 ? -1 : mk);
+    return mac_variant_multi(ctx, ly, B, (mk == 7 || mk == 8) ? -1 : mk);
 }
 
 // Times one kernel launch with dispatch-recorded events when profiling is on for its kind.
@@ -693,6 +701,7 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         if (mac_fused_ok(ctx, ly)) macs.push_back(2);
         if (mac_lds_ok(ly, B))
             for (int m : {3, 4, 5, 6}) macs.push_back(m);
+        if (mac_mfma_layer_ok(ly, B)) macs.push_back(9);
         if (layer_one_launch_ok(ctx, ly, B, nullptr)) macs.push_back(7);
         if (layer_one_launch_ok(ctx, ly, B, nullptr, true)) macs.push_back(8);
         trial.mac_layer = ly;
@@ -705,7 +714,7 @@ int he_autotune_layer(he_ctx *ctx, const he_layer *ly, uint32_t B, void *stream)
         // shared by the layers of one shape, and the first of them would otherwise see the default
         if (rc == HE_OK && cls && logm >= 4) {
             const int mv = mac_variant(ctx, ly, B);
-            if (mv == 2 || mv >= 7) trial.mac = 0;
+            if (mv == 2 || mv == 7 || mv == 8) trial.mac = 0;
             rc = pick(knob_setter(HE_TUNE_TAIL, logm, rows), radix, true, &chosen);
             trial.mac = -1;
         }
@@ -1262,7 +1271,7 @@ int conv_from_x(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *xn,
     const uint32_t Juse = has_sh ? Jtot : K_in;
     const bool cls = in.flags == HE_PACK_CLASS_INTT;
     int mk = mac_variant(ctx, ly, B);
-    if (mk >= 7) mk = mac_variant_multi(ctx, ly, B, -1);   // no sync block here: the multi-launch rule
+    if (mk == 7 || mk == 8) mk = mac_variant_multi(ctx, ly, B, -1);   // no sync block here: the multi-launch rule
     if (mk == 2) {
         // a2 + a3 + a4 in one launch: MAC, residue-class inverse, extraction, + Delta sh'
         ProfScope ps(ctx, HE_K_MAC_TAIL);
@@ -1273,11 +1282,13 @@ int conv_from_x(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *xn,
     }
     {
         const bool tiled = mk == 1;
-        ProfScope ps(ctx, HE_K_MAC);
+        ProfScope ps(ctx, mk == 9 ? HE_K_MAC_MFMA : HE_K_MAC);
         if (mk == 3 || mk == 4)
             e = launch_mac_lds(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, mk == 4, ctx->lc, st, ps.ev());
         else if (mk == 5 || mk == 6)
             e = launch_mac_dma(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, mk == 6, ctx->lc, st, ps.ev());
+        else if (mk == 9)
+            e = launch_mac_mfma(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, ctx->lc, st, ps.ev());
         else if (tiled)
             e = launch_mac_tiled(xn, ly->op, mac, B, Jtot, Juse, c_o, L, N, in.s, cls, ctx->lc, st, ps.ev());
         else if (cls)
@@ -1292,7 +1303,8 @@ int conv_from_x(he_ctx *ctx, const he_layer *ly, uint32_t B, const uint32_t *xn,
         ProfScope ps(ctx, HE_K_TAIL);
         if (logm >= 4)
             e = launch_tail_rows(mac, d_out, d_sh_next, B, c_o, in.g_o, in.K_out, L, N, in.s, ctx->twi, ctx->twish,
-                                 ctx->lc, st, ps.ev(), knob(ctx, HE_TUNE_TAIL, logm, B * in.K_out * in.g_o * L));
+                                 ctx->lc, st, ps.ev(), knob(ctx, HE_TUNE_TAIL, logm, B * in.K_out * in.g_o * L),
+                                 mk == 9);
         else
             e = launch_tail_class(mac, d_out, d_sh_next, B, c_o, in.g_o, in.K_out, L, N, in.s, ctx->twi, ctx->twish,
                                   ctx->lc, st, ps.ev());

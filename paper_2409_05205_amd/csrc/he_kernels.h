@@ -94,11 +94,12 @@ hipError_t launch_tail_class(const uint32_t *h, uint32_t *out, const uint32_t *s
                              hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Residue-class tail on registers: one (N/s)-point inverse per channel vector, several
-// channel vectors per workgroup, coalesced scatter into the output poly (N/s >= 16).
+// channel vectors per workgroup, coalesced scatter into the output poly (N/s >= 16).  The
+// block sums are h[b][n][l][m], or h[l][m][b][n] with by_block (the matrix-core MAC's output).
 hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
                             uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
-                            const LaunchEv *ev = nullptr, int logr = 0);
+                            const LaunchEv *ev = nullptr, int logr = 0, bool by_block = false);
 
 // LDS-staged batched MAC, residue-class form (s >= 2): same output as launch_mac_class.
 struct MacLdsGeom {
@@ -122,6 +123,15 @@ size_t mac_dma_lds_bytes(const MacLdsGeom &gm);
 hipError_t launch_mac_dma(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
                           uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, bool xcd_order,
                           const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
+
+// The same block sums on the integer matrix cores (kernels_mac_mfma.hip): residues split into
+// signed base-256 digits, digit-plane products accumulated exactly in i32, written block-major
+// (h[l][m][b][n], for launch_tail_rows with by_block).  Needs s a power of two >= 4, N/s >= 16
+// and Juse s <= 32768 (mac_mfma_ok).
+bool mac_mfma_ok(uint32_t B, uint32_t Juse, uint32_t N, uint32_t s);
+hipError_t launch_mac_mfma(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
+                           uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
+                           hipStream_t st, const LaunchEv *ev = nullptr);
 
 // Fused class-form MAC + residue-class tail: one workgroup per output row
 // (b, g, n', l); same output as launch_mac_class followed by launch_tail_rows.

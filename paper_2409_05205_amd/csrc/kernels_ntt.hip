@@ -310,7 +310,7 @@ template <int LOGM, int LOGR>
 __global__ void __launch_bounds__((tail_tpw<LOGM, LOGR>()))
 k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const uint32_t *__restrict__ sh_next,
             uint32_t B, uint32_t c_o, uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, uint32_t RW,
-            const uint32_t *__restrict__ twi, const uint32_t *__restrict__ twish, LimbConsts lc) {
+            const uint32_t *__restrict__ twi, const uint32_t *__restrict__ twish, LimbConsts lc, uint32_t by_block) {
     constexpr int M = 1 << LOGM;
     constexpr int T = 1 << (LOGM - LOGR);
     constexpr int MP = M + (M >> 5);
@@ -344,12 +344,23 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
     const uint32_t c_lo = np0 << cw_log;
     const uint32_t *sh = sh_next ? sh_next + (size_t)(b * K_out + g) * N : nullptr;
     const uint32_t total = (uint32_t)M << span_log;
-    if (active) {
-        const uint32_t *src = h + ((size_t)(b * c_o + (exists ? n : 0)) * L + l) * M;
+    if (!by_block) {
+        if (active) {
+            const uint32_t *src = h + ((size_t)(b * c_o + (exists ? n : 0)) * L + l) * M;
 #pragma unroll
-        for (int i = 0; i < (1 << LOGR); ++i) {
-            const uint32_t idx = t + i * T;
-            my[lpad(idx)] = exists ? src[idx] : 0u;
+            for (int i = 0; i < (1 << LOGR); ++i) {
+                const uint32_t idx = t + i * T;
+                my[lpad(idx)] = exists ? src[idx] : 0u;
+            }
+        }
+    } else {
+        // block-major sums h[l][m][b][n]: the workgroup's RW channels of one block are adjacent
+        const uint32_t rw_log = 31u - __clz(RW);
+        const uint32_t nb = g * g_o + np0;
+        const uint32_t *src = h + ((size_t)l * M * B + b) * c_o + nb;
+        for (uint32_t e = tid; e < ((uint32_t)M << rw_log); e += blockDim.x) {
+            const uint32_t r = e & (RW - 1u), idx = e >> rw_log;
+            lds[r * MP + lpad(idx)] = nb + r < c_o ? src[(size_t)idx * B * c_o + r] : 0u;
         }
     }
     // the sh' words of the first 16 write rounds, fetched now so that they arrive during the inverse
@@ -393,7 +404,8 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
 template <int LOGM, int LOGR>
 hipError_t tail_launch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
                        uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t logN, uint32_t s_log, const uint32_t *twi,
-                       const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev) {
+                       const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev,
+                       uint32_t by_block) {
     if constexpr (valid_variant(LOGM, LOGR)) {
         constexpr int T = 1 << (LOGM - LOGR);
         constexpr int TPW = tail_tpw<LOGM, LOGR>();
@@ -402,7 +414,7 @@ hipError_t tail_launch(const uint32_t *h, uint32_t *out, const uint32_t *sh_next
         const uint32_t grid = xcd_grid(B * K_out * L * (g_o / RW));
         const size_t lds = (size_t)(TPW / T) * ((1u << LOGM) + (1u << LOGM >> 5)) * sizeof(uint32_t);
         HE_LAUNCH(ev, (k_tail_rows<LOGM, LOGR>), dim3(grid), dim3(TPW), lds, st, h, out, sh_next, B, c_o, g_o,
-                  K_out, L, logN, s_log, RW, twi, twish, lc);
+                  K_out, L, logN, s_log, RW, twi, twish, lc, by_block);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -593,7 +605,7 @@ hipError_t launch_ntt_inv(int logn, const uint32_t *src, uint32_t *dst, const Ro
 hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
                             uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st, const LaunchEv *ev,
-                            int logr) {
+                            int logr, bool by_block) {
     if (B == 0) return hipSuccess;
     uint32_t logN = 0, s_log = 0;
     while ((1u << logN) < N) ++logN;
@@ -605,7 +617,8 @@ hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh
         logr = rows >= 1024 ? (logm <= 12 ? 4 : 5) : (logm - 8 > 2 ? logm - 8 : 2);   // few rows: 256 threads/row
         if (logr > logm) logr = logm;
     }
-#define HE_TAIL(LM, LR) tail_launch<LM, LR>(h, out, sh_next, B, c_o, g_o, K_out, L, logN, s_log, twi, twish, lc, st, ev)
+#define HE_TAIL(LM, LR) \
+    tail_launch<LM, LR>(h, out, sh_next, B, c_o, g_o, K_out, L, logN, s_log, twi, twish, lc, st, ev, by_block ? 1u : 0u)
     switch (logm) {
         case 4: HE_SWITCH_LOGR(4, logr, HE_TAIL)
         case 5: HE_SWITCH_LOGR(5, logr, HE_TAIL)

@@ -44,6 +44,7 @@ NOALLOC_SCRATCH_BYTES = 32 << 20   # HE_NOALLOC_SCRATCH_BYTES in include/he.h
 HE_TUNE_NTT_FWD, HE_TUNE_NTT_INV, HE_TUNE_TAIL, HE_TUNE_MAC = 1, 2, 3, 4
 HE_K_NTT_FWD, HE_K_MAC, HE_K_TAIL, HE_K_INTT, HE_K_MAC_TAIL, HE_K_LAYER, HE_K_LAYER_ROWS = 1, 2, 4, 8, 16, 32, 64
 HE_K_GROUP = 128
+HE_K_MAC_MFMA = 256
 HE_GROUP_MAC_AUTO, HE_GROUP_MAC_PER_IMAGE, HE_GROUP_MAC_TILED = 0, 1, 2
 
 

@@ -1,5 +1,6 @@
 """GPU parity of the LDS-staged batched MAC (HE_TUNE_MAC = 3, and 4 with XCD-contiguous
-workgroup order; 5 and 6 the same with the stages moved by LDS DMA) against the oracle:
+workgroup order; 5 and 6 the same with the stages moved by LDS DMA; 9 the matrix-core form,
+which the layers with s = 2 leave for the streaming one) against the oracle:
 every staging geometry its host planner produces (one or several slot groups
 per block, stages that hold whole blocks or part of one, image and channel tiles
 wider than the batch or the layer), ragged batches and channel counts, with and
@@ -52,7 +53,7 @@ def test_lds_mac_matches_oracle(he, case):
     for use_sh in (True, False):
         want = [bfv.server_conv(octx, g, c0[b].astype(np.uint64), rho, fh, sh[b] if use_sh else None, shn[b])
                 for b in range(B)]
-        for mac in (3, 4, 5, 6):    # register / DMA staging, round-robin / XCD-contiguous order
+        for mac in (3, 4, 5, 6, 9):    # register / DMA staging, round-robin / XCD-contiguous order; matrix cores
             ctx.tune_force(he.HE_TUNE_MAC, mac)
             got = host(ctx.conv_layer(layer, dev(c0), dev(sh) if use_sh else None, dev(shn)))
             for b in range(B):

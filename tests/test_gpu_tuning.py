@@ -43,7 +43,7 @@ def _case(N, L, c_i, c_o, H, stride, seed, B):
 
 
 @pytest.mark.parametrize("knob_name,values", [("HE_TUNE_NTT_FWD", [2, 3, 4, 5]), ("HE_TUNE_TAIL", [2, 3, 4, 5]),
-                                              ("HE_TUNE_NTT_INV", [2, 3, 4, 5]), ("HE_TUNE_MAC", [0, 1, 2, 3, 4, 5, 6])])
+                                              ("HE_TUNE_NTT_INV", [2, 3, 4, 5]), ("HE_TUNE_MAC", [0, 1, 2, 3, 4, 5, 6, 9])])
 def test_knob_sweep_is_exact(he, knob_name, values):
     N, L = 1024, 2
     knob = getattr(he, knob_name)
