@@ -20,7 +20,7 @@
 // reduced.  The words are the same as every other MAC form's.
 //
 // Tiling.  A workgroup of 256 threads (4 waves) owns 64 images x 64 channels of one limb and
-// 2^mb_log consecutive blocks.  Per chunk of 64 K elements, each thread loads 16 words of one
+// 2^mb_log consecutive blocks (one, at the shapes measured).  Per chunk of 64 K elements, each thread loads 16 words of one
 // image row and 16 of one channel row (4 x 16 bytes each, a row's slots being contiguous for
 // s >= 4), converts them to digit planes and stores those to LDS (rows padded to 80 bytes, so that
 // the 16-byte operand reads of 8 consecutive rows fall in distinct banks).  Each wave then
@@ -199,9 +199,11 @@ hipError_t launch_mac_mfma(const uint32_t *X, const uint32_t *Op, uint32_t *h, u
     while ((1u << s_log) < s) ++s_log;
     const uint32_t M = N >> s_log;
     const uint32_t tiles_b = (B + MM_T - 1) / MM_T, tiles_n = (c_o + MM_T - 1) / MM_T;
-    // blocks per workgroup: as many as keep about 2048 workgroups (a few per CU), at most 16
+    // blocks per workgroup: one unless the grid would exceed 16384 workgroups.  On the x4 stack
+    // (L = 6, 2048 blocks) one block per workgroup ran the s = 8 layers in 445 us against 590 us
+    // with four and 583 us with sixteen: the shorter workgroups fill the CUs more evenly
     uint32_t mb_log = 0;
-    while (mb_log < 4 && (M >> (mb_log + 1)) >= 1 && (uint64_t)L * (M >> (mb_log + 1)) * tiles_b * tiles_n >= 2048)
+    while (mb_log < 4 && (M >> (mb_log + 1)) >= 1 && (uint64_t)L * (M >> (mb_log + 1)) * tiles_b * tiles_n >= 16384)
         ++mb_log;
     const uint32_t tiles = L * (M >> mb_log) * tiles_b * tiles_n;
     HE_LAUNCH(ev, k_mac_mfma, dim3(xcd_grid(tiles)), dim3(MM_THREADS), 0, st, X, Op, h, B, Jtot, Juse, c_o, L, N,
