@@ -283,7 +283,7 @@ bool mac_lds_ok(const he_layer *ly, uint32_t B) {
 // slots per block (the sum over rows of one block at most 32768 products)
 bool mac_mfma_layer_ok(const he_layer *ly, uint32_t B) {
     const he_layer_info &in = ly->info;
-    return mac_lds_ok(ly, B) && mac_mfma_ok(B, 2 * in.K_in, in.N, in.s);
+    return mac_lds_ok(ly, B) && mac_mfma_ok(B, ly->n_rows, 2 * in.K_in, in.N, in.s);
 }
 
 // The item geometry of this layer at batch B in the one-launch / grouped forms (kernels_fused.hip),

@@ -95,7 +95,8 @@ hipError_t launch_tail_class(const uint32_t *h, uint32_t *out, const uint32_t *s
 
 // Residue-class tail on registers: one (N/s)-point inverse per channel vector, several
 // channel vectors per workgroup, coalesced scatter into the output poly (N/s >= 16).  The
-// block sums are h[b][n][l][m], or h[l][m][b][n] with by_block (the matrix-core MAC's output).
+// block sums are h[b][n][l][m], or h[l][b][n / 8][m][n % 8] with by_block (the matrix-core
+// MAC's output; c_o a multiple of 8).
 hipError_t launch_tail_rows(const uint32_t *h, uint32_t *out, const uint32_t *sh_next, uint32_t B, uint32_t c_o,
                             uint32_t g_o, uint32_t K_out, uint32_t L, uint32_t N, uint32_t s, const uint32_t *twi,
                             const uint32_t *twish, const LimbConsts &lc, hipStream_t st,
@@ -125,10 +126,10 @@ hipError_t launch_mac_dma(const uint32_t *X, const uint32_t *Op, uint32_t *h, ui
                           const LimbConsts &lc, hipStream_t st, const LaunchEv *ev = nullptr);
 
 // The same block sums on the integer matrix cores (kernels_mac_mfma.hip): residues split into
-// signed base-256 digits, digit-plane products accumulated exactly in i32, written block-major
-// (h[l][m][b][n], for launch_tail_rows with by_block).  Needs s a power of two >= 4, N/s >= 16
-// and Juse s <= 32768 (mac_mfma_ok).
-bool mac_mfma_ok(uint32_t B, uint32_t Juse, uint32_t N, uint32_t s);
+// signed base-256 digits, digit-plane products accumulated exactly in i32, written in groups of 8
+// channels (h[l][b][n / 8][m][n % 8], for launch_tail_rows with by_block).  Needs c_o a multiple
+// of 8, s a power of two >= 4, N/s >= 16 and Juse s <= 32768 (mac_mfma_ok).
+bool mac_mfma_ok(uint32_t B, uint32_t c_o, uint32_t Juse, uint32_t N, uint32_t s);
 hipError_t launch_mac_mfma(const uint32_t *X, const uint32_t *Op, uint32_t *h, uint32_t B, uint32_t Jtot,
                            uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
                            hipStream_t st, const LaunchEv *ev = nullptr);

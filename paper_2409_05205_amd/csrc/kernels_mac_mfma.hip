@@ -2,13 +2,14 @@
 //
 // For a layer at batch B the block sums the residue-class tail reads are, for every limb l and
 // block m (the s consecutive NTT slots [m s, m s + s)),
-//     h[l][m][b][n] = sum over input rows j < Juse and slots k of block m of
+//     H(b, n, l, m) = sum over input rows j < Juse and slots k of block m of
 //                     X[b][j][l][k] * Op[n][l][j][k]  mod q_l,
 // a product of a B x K matrix (images by (row, slot) pairs, K = Juse s) with a K x c_o one
 // (operands by output channel): a dense contraction, which this kernel runs on the integer matrix
-// cores (v_mfma_i32_16x16x64_i8).  The sums are stored block-major, as above (the tail reads that
-// order with its by_block option): a block's 64 x 64 tile then goes out as 64-byte row segments,
-// where the image-major order of the other MAC forms would scatter it into 4-byte writes.
+// cores (v_mfma_i32_16x16x64_i8).  The sums are stored in groups of 8 channels,
+// h[l][b][n / 8][m][n % 8] (the tail reads that order with its by_block option): a block's tile
+// then goes out as 32-byte pieces, where the order of the other MAC forms, h[b][n][l][m], would
+// scatter it into 4-byte writes that no L2 holds until the neighbouring blocks fill them.
 //
 // Exactness.  Every residue x < q < 2^30 is written in signed base-256 digits,
 //     x = d0 + d1 2^8 + d2 2^16 + d3 2^24,  d0, d1, d2 in [-128, 128), d3 in [0, 64],
@@ -174,7 +175,7 @@ k_mac_mfma(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint
                         const uint32_t rh = reduce_signed56(hi, off, c);
                         const uint32_t v = csub(rl + csub(shoup_lazy(rh, c.r32, c.r32_sh, c.q), c.q), c.q);
                         const uint32_t b = b0 + rb + 16u * r + 4u * lg + e, n = n0 + cb + 16u * cc + li;
-                        if (b < B && n < c_o) h[((size_t)(l * M + m) * B + b) * c_o + n] = v;
+                        if (b < B && n < c_o) h[(((size_t)(l * B + b) * c_o + (n & ~7u)) * M + m * 8u) + (n & 7u)] = v;
                     }
 #pragma unroll
                     for (int s = 0; s < 7; ++s) acc[r][cc][s] = v4i{0, 0, 0, 0};
@@ -185,8 +186,8 @@ k_mac_mfma(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint
 
 }  // namespace
 
-bool mac_mfma_ok(uint32_t B, uint32_t Juse, uint32_t N, uint32_t s) {
-    return B >= 1 && Juse >= 1 && s >= 4 && (s & (s - 1)) == 0 && 16 * s <= N && N >= 256 && (N & (N - 1)) == 0 &&
+bool mac_mfma_ok(uint32_t B, uint32_t c_o, uint32_t Juse, uint32_t N, uint32_t s) {
+    return B >= 1 && c_o >= 8 && c_o % 8 == 0 && Juse >= 1 && s >= 4 && (s & (s - 1)) == 0 && 16 * s <= N && N >= 256 && (N & (N - 1)) == 0 &&
            (uint64_t)Juse * s <= MM_KMAX;
 }
 
@@ -194,7 +195,7 @@ hipError_t launch_mac_mfma(const uint32_t *X, const uint32_t *Op, uint32_t *h, u
                            uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s, const LimbConsts &lc,
                            hipStream_t st, const LaunchEv *ev) {
     if (B == 0) return hipSuccess;
-    if (c_o == 0 || Juse == 0 || Juse > Jtot || !mac_mfma_ok(B, Juse, N, s)) return hipErrorInvalidValue;
+    if (Juse == 0 || Juse > Jtot || !mac_mfma_ok(B, c_o, Juse, N, s)) return hipErrorInvalidValue;
     uint32_t s_log = 0;
     while ((1u << s_log) < s) ++s_log;
     const uint32_t M = N >> s_log;

@@ -354,13 +354,15 @@ k_tail_rows(const uint32_t *__restrict__ h, uint32_t *__restrict__ out, const ui
             }
         }
     } else {
-        // block-major sums h[l][m][b][n]: the workgroup's RW channels of one block are adjacent
+        // sums in groups of 8 channels, h[l][b][n / 8][m][n % 8] (c_o a multiple of 8): a block's
+        // words of 8 channels are adjacent, so the workgroups of neighbouring channels, which run
+        // together, read whole 32-byte pieces between them
         const uint32_t rw_log = 31u - __clz(RW);
         const uint32_t nb = g * g_o + np0;
-        const uint32_t *src = h + ((size_t)l * M * B + b) * c_o + nb;
+        const uint32_t *src = h + (size_t)(l * B + b) * c_o * M;
         for (uint32_t e = tid; e < ((uint32_t)M << rw_log); e += blockDim.x) {
-            const uint32_t r = e & (RW - 1u), idx = e >> rw_log;
-            lds[r * MP + lpad(idx)] = nb + r < c_o ? src[(size_t)idx * B * c_o + r] : 0u;
+            const uint32_t r = e & (RW - 1u), idx = e >> rw_log, n = nb + r;
+            lds[r * MP + lpad(idx)] = n < c_o ? src[((size_t)(n >> 3) * M + idx) * 8u + (n & 7u)] : 0u;
         }
     }
     // the sh' words of the first 16 write rounds, fetched now so that they arrive during the inverse
