@@ -67,39 +67,39 @@ PMC_TRAFFIC = {
     "layers": {
         "forms": {
             "F": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "1ad4e747fc0daf9ca6d0705f8b203b15035e47c18c9c838ec398ef1ad9613f29"},
+                  "sha256": "8d1ea5ef077d446825896ff12ca053fd17508c6d584bab342ab22c7bc30a3008"},
             "S": {"sources": ['paper_2409_05205_amd/csrc/kernels_mac.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "9979c72f0e5bd3f8d074c26d9a20ff0e9f2023704aba631fe05efecaf90ecfe7"},
+                  "sha256": "a7faeb2207bf7d8972ef6a84f4dce52fd05e94139fd72f17b001672f5dfcbb0c"},
             "O": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "3fa3dc15a11e9bff84a373a56ef09389b6c319e7d90280a9f7a5725e1d38aee3"},
+                  "sha256": "645ce1a77c03a9d6853cd08c333e990aea30effd7100a5746eaf85749a3bdfb6"},
             "R": {"sources": ['paper_2409_05205_amd/csrc/kernels_fused.hip', 'paper_2409_05205_amd/csrc/mac_device.h', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h', 'paper_2409_05205_amd/csrc/he_kernels.h'],
-                  "sha256": "3fa3dc15a11e9bff84a373a56ef09389b6c319e7d90280a9f7a5725e1d38aee3"},
+                  "sha256": "645ce1a77c03a9d6853cd08c333e990aea30effd7100a5746eaf85749a3bdfb6"},
         },
         "per_layer": [
-            {"F": 4729513, "S": 2793489, "O": 8169392, "R": 5412203},
-            {"F": 21239908, "S": 18389307, "O": 27300482, "R": 24147335},
-            {"F": 21239871, "S": 18389014, "O": 27303261, "R": 24146238},
-            {"F": 21239871, "S": 18389014, "O": 27300628, "R": 24146257},
-            {"F": 21239816, "S": 18389014, "O": 27299659, "R": 24146183},
-            {"F": 21240109, "S": 18389051, "O": 27299641, "R": 24146823},
-            {"F": 21239889, "S": 18389014, "O": 27301176, "R": 24146238},
-            {"F": 40111469, "S": 35688734, "O": 48296852, "R": 43045682},
-            {"F": 19041012, "S": 17602865, "O": 22430549, "R": 20821057},
-            {"F": 19040866, "S": 17602646, "O": 22433328, "R": 20820801},
-            {"F": 19041030, "S": 17602792, "O": 22433493, "R": 20820929},
-            {"F": 19040847, "S": 17602646, "O": 22432268, "R": 20820947},
-            {"F": 19040975, "S": 17602646, "O": 22432396, "R": 20820929},
-            {"F": 36864137, "S": 34641246, "O": 41334044, "R": 38816318},
-            {"F": 17950495, "S": 17209462, "O": 19852529, "R": 19245560},
-            {"F": 17950440, "S": 17209462, "O": 19853023, "R": 19276496},
-            {"F": 17950386, "S": 17209462, "O": 19851249, "R": 19262765},
-            {"F": 17950642, "S": 17209608, "O": 19848397, "R": 19266934},
-            {"F": 17950148, "S": 17209315, "O": 19851981, "R": 19249308},
-            {"F": None, "S": 704442, "O": 2252190, "R": 2253363},
+            {"F": 4734832, "S": 2794366, "O": 8171361, "R": 5412329},
+            {"F": 21246894, "S": 18389014, "O": 27299716, "R": 24147928},
+            {"F": 21246693, "S": 18389014, "O": 27304469, "R": 24146264},
+            {"F": 21246657, "S": 18389014, "O": 27301124, "R": 24146173},
+            {"F": 21246492, "S": 18389014, "O": 27299021, "R": 24146191},
+            {"F": 21246565, "S": 18389069, "O": 27301763, "R": 24146721},
+            {"F": 21246492, "S": 18389014, "O": 27302513, "R": 24146228},
+            {"F": 40117782, "S": 35688643, "O": 48298221, "R": 43046101},
+            {"F": 19031735, "S": 17602847, "O": 22431035, "R": 20820773},
+            {"F": 19031204, "S": 17602646, "O": 22431638, "R": 20820627},
+            {"F": 19031332, "S": 17602792, "O": 22431967, "R": 20820773},
+            {"F": 19031460, "S": 17602646, "O": 22430632, "R": 20820773},
+            {"F": 19031479, "S": 17602646, "O": 22430523, "R": 20820810},
+            {"F": 36854486, "S": 34641026, "O": 41334202, "R": 38794379},
+            {"F": 17956058, "S": 17209462, "O": 19849457, "R": 19257527},
+            {"F": 17956003, "S": 17209462, "O": 19850371, "R": 19257454},
+            {"F": 17956039, "S": 17209462, "O": 19852748, "R": 19262811},
+            {"F": 17956167, "S": 17209608, "O": 19849859, "R": 19261823},
+            {"F": 17956039, "S": 17209315, "O": 19852620, "R": 19257472},
+            {"F": None, "S": 704442, "O": 2251866, "R": 2253143},
         ]},
     "ntt_fwd": {"sources": ['paper_2409_05205_amd/csrc/kernels_ntt.hip', 'paper_2409_05205_amd/csrc/ntt_device.h', 'paper_2409_05205_amd/csrc/he_device.h'],
-                "sha256": "49292b8e7dd98223913862ab1c3c1ae2c3e9afcbc77088f7fd93d3c857110c67",
-                "bytes_per_launch": 2834223},
+                "sha256": "c280e448cab85526766aa78838073e79e0eb9474054d251a16fa52e20c135e11",
+                "bytes_per_launch": 2834205},
 }
 
 
