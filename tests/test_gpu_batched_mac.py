@@ -25,6 +25,8 @@ CASES = [
     (2048, 8, 8, 2, 1, 2),       # s = 128, several stages per block, two groups per block
     (4096, 16, 32, 2, 2, 4),     # s = 256
     (1024, 8, 64, 2, 1, 9),      # s = 64, many channels
+    (1024, 8, 24, 6, 1, 5),      # s = 64, channels a multiple of 8 but not of 64 (matrix-core tile)
+    (4096, 1024, 8, 6, 1, 3),    # s = 64, K_in = 16: 2048 products per block sum (32 matrix-core chunks)
 ]
 
 
