@@ -35,12 +35,25 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int MM_THREADS = 256;
-constexpr int MM_T = 64;                     // images and channels per workgroup tile
+constexpr int MM_T = 64;                     // images per workgroup tile
 constexpr int MM_KC = 64;                    // K elements per chunk
 constexpr int MM_ROWB = 80;                  // bytes per staged row (64 digit bytes + 16 pad)
-constexpr int MM_PLANE = MM_T * MM_ROWB;     // bytes per digit plane of one operand
-constexpr int MM_LDS = 8 * MM_PLANE;         // 4 planes of images, 4 of channels
+constexpr int MM_XPL = MM_T * MM_ROWB;       // bytes per digit plane of the image rows
 constexpr uint32_t MM_KMAX = 32768;          // longest exact contraction
+
+// Channel tile TN = 64, 32 or 16 (layers of fewer channels take the narrower tiles, which hold
+// fewer accumulators and so run more workgroups per CU).  The 4 waves split the 64 x TN tile
+// WR (images) by WC (channels); each wave owns RT x CT MFMA tiles of 16 x 16.
+template <int TN>
+struct MMShape {
+    static constexpr int WC = TN >= 32 ? 2 : 1;
+    static constexpr int WR = 4 / WC;
+    static constexpr int CT = TN / (16 * WC);
+    static constexpr int RT = MM_T / (16 * WR);
+    static constexpr int OPL = TN * MM_ROWB;                 // bytes per digit plane of the channel rows
+    static constexpr int LDS = 4 * MM_XPL + 4 * OPL;
+    static constexpr int WG_PER_CU = TN == 64 ? 2 : (TN == 32 ? 3 : 4);
+};
 
 // signed base-256 digits of x < 2^30, one per byte
 __device__ __forceinline__ uint32_t sdigits(uint32_t x) { return (x + 0x00808080u) ^ 0x00808080u; }
@@ -63,11 +76,14 @@ __device__ __forceinline__ uint32_t reduce_signed56(int64_t v, uint64_t off, con
     return reduce64((uint64_t)(v + (int64_t)off), c);
 }
 
-__global__ void __launch_bounds__(MM_THREADS, 2)
+template <int TN>
+__global__ void __launch_bounds__(MM_THREADS, MMShape<TN>::WG_PER_CU)
 k_mac_mfma(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint32_t *__restrict__ h, uint32_t B,
            uint32_t Jtot, uint32_t Juse, uint32_t c_o, uint32_t L, uint32_t N, uint32_t s_log, uint32_t mb_log,
            uint32_t tiles_b, uint32_t tiles_n, LimbConsts lc) {
-    __shared__ __align__(16) uint8_t lds[MM_LDS];
+    using S = MMShape<TN>;
+    constexpr int RT = S::RT, CT = S::CT;
+    __shared__ __align__(16) uint8_t lds[S::LDS];
     const uint32_t M = N >> s_log;
     const uint32_t ranges = M >> mb_log;
     uint32_t w;
@@ -79,12 +95,14 @@ k_mac_mfma(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint
     const uint32_t mr = w % ranges;
     const uint32_t l = w / ranges;
     const LimbConst c = lc.l[l];
-    const uint32_t b0 = tb * MM_T, n0 = tn * MM_T;
+    const uint32_t b0 = tb * MM_T, n0 = tn * TN;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
 
-    // staging role: image / channel row tid / 4, K quarter tid % 4 (16 elements)
+    // staging role: image row tid / 4 and, for the first 4 TN threads, channel row tid / 4; K
+    // quarter tid % 4 (16 elements)
     const uint32_t srow = tid >> 2, sq = tid & 3u;
-    const bool xv = b0 + srow < B, ov = n0 + srow < c_o;
+    const bool ostage = srow < (uint32_t)TN;
+    const bool xv = b0 + srow < B, ov = ostage && n0 + srow < c_o;
     const uint32_t *xrow = X + ((size_t)(xv ? b0 + srow : 0) * Jtot * L + l) * N;    // + (j L) N + slot
     const uint32_t *orow = Op + ((size_t)(ov ? n0 + srow : 0) * L + l) * Jtot * N;   // + j N + slot
     const uint32_t K = Juse << s_log;
@@ -105,56 +123,59 @@ k_mac_mfma(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint
             po[u] = (in && ov) ? *reinterpret_cast<const uint4 *>(orow + (size_t)j * N + slot) : make_uint4(0, 0, 0, 0);
         }
     };
+    auto stage = [&](const uint4 (&pv)[4], uint8_t *base, int plane_bytes) {
+        uint32_t pl[4][4];   // [plane][u]
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uint32_t p[4];
+            planes4(pv[u], p);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) pl[a][u] = p[a];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            *reinterpret_cast<uint4 *>(base + a * plane_bytes) = make_uint4(pl[a][0], pl[a][1], pl[a][2], pl[a][3]);
+    };
 
-    // product role: wave corner (32 images, 32 channels); lane row / column li, K group lg
+    // product role: the wave's RT x CT tiles; lane row / column li, K group lg
     const uint32_t li = lane & 15u, lg = lane >> 4;
-    const uint32_t rb = 32u * (wave & 1u), cb = 32u * (wave >> 1);
-    v4i acc[2][2][7];
+    const uint32_t rb = 16u * RT * (wave % S::WR), cb = 16u * CT * (wave / S::WR);
+    v4i acc[RT][CT][7];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < CT; ++j)
 #pragma unroll
             for (int s = 0; s < 7; ++s) acc[i][j][s] = v4i{0, 0, 0, 0};
     const uint64_t off = (uint64_t)c.q << (25 + __clz(c.q));   // a multiple of q in [2^56, 2^57)
+    uint8_t *const lx = lds, *const lo_ = lds + 4 * MM_XPL;
 
     load(0);
     for (uint32_t qi = 0; qi < total; ++qi) {
         __syncthreads();   // every wave is done reading the previous chunk's planes
-#pragma unroll
-        for (int op = 0; op < 2; ++op) {
-            uint32_t pl[4][4];   // [plane][u]
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                uint32_t p[4];
-                planes4(op == 0 ? px[u] : po[u], p);
-#pragma unroll
-                for (int a = 0; a < 4; ++a) pl[a][u] = p[a];
-            }
-            uint8_t *base = lds + op * 4 * MM_PLANE + srow * MM_ROWB + sq * 16u;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-                *reinterpret_cast<uint4 *>(base + a * MM_PLANE) = make_uint4(pl[a][0], pl[a][1], pl[a][2], pl[a][3]);
-        }
+        stage(px, lx + srow * MM_ROWB + sq * 16u, MM_XPL);
+        if (ostage) stage(po, lo_ + srow * MM_ROWB + sq * 16u, S::OPL);
         __syncthreads();   // the planes of this chunk are in LDS
         if (qi + 1 < total) load(qi + 1);
 
-        v4i A[2][4], Bm[2][4];
+        v4i A[RT][4], Bm[CT][4];
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int a = 0; a < 4; ++a) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                A[r][a] = *reinterpret_cast<const v4i *>(lds + a * MM_PLANE + (rb + 16u * r + li) * MM_ROWB + 16u * lg);
-                Bm[r][a] = *reinterpret_cast<const v4i *>(lds + (4 + a) * MM_PLANE + (cb + 16u * r + li) * MM_ROWB + 16u * lg);
-            }
+            for (int r = 0; r < RT; ++r)
+                A[r][a] = *reinterpret_cast<const v4i *>(lx + a * MM_XPL + (rb + 16u * r + li) * MM_ROWB + 16u * lg);
+#pragma unroll
+            for (int cc = 0; cc < CT; ++cc)
+                Bm[cc][a] = *reinterpret_cast<const v4i *>(lo_ + a * S::OPL + (cb + 16u * cc + li) * MM_ROWB + 16u * lg);
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int bd = 0; bd < 4; ++bd)
 #pragma unroll
-                for (int r = 0; r < 2; ++r)
+                for (int r = 0; r < RT; ++r)
 #pragma unroll
-                    for (int cc = 0; cc < 2; ++cc)
+                    for (int cc = 0; cc < CT; ++cc)
                         acc[r][cc][a + bd] =
                             __builtin_amdgcn_mfma_i32_16x16x64_i8(A[r][a], Bm[cc][bd], acc[r][cc][a + bd], 0, 0, 0);
 
@@ -162,9 +183,9 @@ k_mac_mfma(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Op, uint
             // block m done: lane holds images rb + 16 r + 4 lg + e, channel cb + 16 cc + li
             const uint32_t m = (mr << mb_log) + qi / nch;
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < RT; ++r)
 #pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
+                for (int cc = 0; cc < CT; ++cc) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int64_t lo = (int64_t)acc[r][cc][0][e] + (int64_t)acc[r][cc][1][e] * 256 +
@@ -199,7 +220,8 @@ hipError_t launch_mac_mfma(const uint32_t *X, const uint32_t *Op, uint32_t *h, u
     uint32_t s_log = 0;
     while ((1u << s_log) < s) ++s_log;
     const uint32_t M = N >> s_log;
-    const uint32_t tiles_b = (B + MM_T - 1) / MM_T, tiles_n = (c_o + MM_T - 1) / MM_T;
+    const uint32_t tn_w = c_o <= 16 ? 16u : (c_o <= 32 ? 32u : 64u);   // channel tile
+    const uint32_t tiles_b = (B + MM_T - 1) / MM_T, tiles_n = (c_o + tn_w - 1) / tn_w;
     // blocks per workgroup: one unless the grid would exceed 16384 workgroups.  On the x4 stack
     // (L = 6, 2048 blocks) one block per workgroup ran the s = 8 layers in 445 us against 590 us
     // with four and 583 us with sixteen: the shorter workgroups fill the CUs more evenly
@@ -207,7 +229,12 @@ hipError_t launch_mac_mfma(const uint32_t *X, const uint32_t *Op, uint32_t *h, u
     while (mb_log < 4 && (M >> (mb_log + 1)) >= 1 && (uint64_t)L * (M >> (mb_log + 1)) * tiles_b * tiles_n >= 16384)
         ++mb_log;
     const uint32_t tiles = L * (M >> mb_log) * tiles_b * tiles_n;
-    HE_LAUNCH(ev, k_mac_mfma, dim3(xcd_grid(tiles)), dim3(MM_THREADS), 0, st, X, Op, h, B, Jtot, Juse, c_o, L, N,
-              s_log, mb_log, tiles_b, tiles_n, lc);
+#define HE_MM(T)                                                                                              \
+    HE_LAUNCH(ev, k_mac_mfma<T>, dim3(xcd_grid(tiles)), dim3(MM_THREADS), 0, st, X, Op, h, B, Jtot, Juse, c_o, L, \
+              N, s_log, mb_log, tiles_b, tiles_n, lc)
+    if (tn_w == 16) HE_MM(16);
+    else if (tn_w == 32) HE_MM(32);
+    else HE_MM(64);
+#undef HE_MM
     return hipGetLastError();
 }
