@@ -458,8 +458,9 @@ void he_server_free(he_server *srv);
  * the whole layer in one launch, forward transforms included, work items in
  * workgroup order that wait on counters), 8 (conv: one launch of whole-row
  * transforms and one MAC + inverse item per output row), 9 (residue-class conv
- * layers, s >= 4: the batched MAC on the integer matrix cores, residues split
- * into signed 8-bit digits whose products are summed exactly) or -1 (automatic:
+ * layers, B >= 2, c_o a multiple of 8, s >= 4 and N/s >= 16: the batched MAC on
+ * the integer matrix cores, residues split into signed 8-bit digits whose
+ * products are summed exactly; a tuner candidate) or -1 (automatic:
  * 7 for FC layers at B = 1 where the shape allows it (N 4096..16384,
  * n_o' <= 1024); for conv layers at B = 1, 2, except 0 for layers with
  * K_in >= 2 and at most 64 output rows K_out g_o L; at B >= 4, 5 for
