@@ -20,13 +20,14 @@
 // two signed 64-bit sums below 2^56 in magnitude, each made positive by a multiple of q and
 // reduced.  The words are the same as every other MAC form's.
 //
-// Tiling.  A workgroup of 256 threads (4 waves) owns 64 images x 64 channels of one limb and
-// 2^mb_log consecutive blocks (one, at the shapes measured).  Per chunk of 64 K elements, each thread loads 16 words of one
-// image row and 16 of one channel row (4 x 16 bytes each, a row's slots being contiguous for
-// s >= 4), converts them to digit planes and stores those to LDS (rows padded to 80 bytes, so that
-// the 16-byte operand reads of 8 consecutive rows fall in distinct banks).  Each wave then
-// computes a 32 x 32 corner of the tile: 2 x 2 MFMA tiles x 16 digit pairs = 64 MFMAs per chunk.
-// The next chunk's global loads are issued before the products, so their latency overlaps them.
+// Tiling.  A workgroup of 256 threads (4 waves) owns 64 images x TN channels (TN = 64, 32 or 16)
+// of one limb and 2^mb_log consecutive blocks (one, at the shapes measured).  Per chunk of 64 K
+// elements, each thread loads 16 words of one image row and the first 4 TN threads 16 of one
+// channel row (4 x 16 bytes each, a row's slots being contiguous for s >= 4), converts them to
+// digit planes and stores those to LDS (rows padded to 80 bytes, so that the 16-byte operand
+// reads of 8 consecutive rows fall in distinct banks).  At TN = 64 each wave then computes a
+// 32 x 32 corner of the tile: 2 x 2 MFMA tiles x 16 digit pairs = 64 MFMAs per chunk.  The next
+// chunk's global loads are issued before the products, so their latency overlaps them.
 
 #include "he_kernels.h"
 
