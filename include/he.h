@@ -463,7 +463,8 @@ void he_server_free(he_server *srv);
  * products are summed exactly; a tuner candidate) or -1 (automatic:
  * 7 for FC layers at B = 1 where the shape allows it (N 4096..16384,
  * n_o' <= 1024); for conv layers at B = 1, 2, except 0 for layers with
- * K_in >= 2 and at most 64 output rows K_out g_o L; at B >= 4, 5 for
+ * K_in >= 2 and at most 64 output rows K_out g_o L; 9 where that form is
+ * allowed and B >= 8 with s >= 16, or B >= 32; otherwise at B >= 4, 5 for
  * residue-class layers and 1 for full-length ones).  The one-launch forms need
  * a counter block: the calls that use a reserved stream workspace,
  * he_conv_layer_noalloc, layer sequences and the server have one, a *_ws call

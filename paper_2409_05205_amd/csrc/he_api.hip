@@ -258,10 +258,11 @@ int mac_tuned(he_ctx *ctx, const he_layer *ly, uint32_t B) {
 // Conv MAC variant of a layer at batch B: 0 streaming (then tail), 1 register-blocked
 // batched (then tail), 2 fused MAC + residue-class tail, 3 LDS-staged batched (then tail),
 // 4 as 3 with XCD-contiguous workgroup order, 5 and 6 as 3 and 4 with the stages moved to LDS
-// by DMA.  A tuned or forced value is used when the layer's shape allows it; otherwise, and by
-// default, B = 1 takes the fused form (the streaming one for layers with K_in >= 2 and at most
-// 64 output rows) and B >= 4 a batched one (5 for the residue-class form, 1 for the
-// full-length form).
+// by DMA, 9 on the matrix cores (then tail).  A tuned or forced value is used when the layer's
+// shape allows it; otherwise, and by default, B = 1 takes the fused form (the streaming one for
+// layers with K_in >= 2 and at most 64 output rows) and B >= 4 a batched one (9 where allowed
+// from B = 8 with s >= 16 and from B = 32 at any s, else 5 for the residue-class form, 1 for
+// the full-length form).
 bool mac_tiled_ok(const he_layer *ly, uint32_t B) {
     const he_layer_info &in = ly->info;
     const bool cls = in.flags == HE_PACK_CLASS_INTT;
@@ -337,6 +338,9 @@ int mac_variant_multi(he_ctx *ctx, const he_layer *ly, uint32_t B, int mk) {
         const he_layer_info &in = ly->info;
         return (in.K_in >= 2 && 4 * in.K_out * in.g_o * in.L <= 256) ? 0 : 2;
     }
+    // the matrix-core form where it was measured faster without tuning: blocks of 16 slots and
+    // more from B = 8, every block length from B = 32 (x1 / x2 / x4 stacks at B = 8, 16, 64)
+    if (B >= 8 && mac_mfma_layer_ok(ly, B) && (ly->info.s >= 16 || B >= 32)) return 9;
     if (B >= 4 && mac_lds_ok(ly, B)) return 5;
     return tiled_ok && B >= 4 ? 1 : 0;
 }
