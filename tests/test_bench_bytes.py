@@ -52,6 +52,9 @@ def test_mac_bytes_and_counts():
     conv = 8 * 16 * L * N * 4 + 64 * 8 * L * N * 4 + 64 * 16 * L * M * 4   # operands, inputs, block sums
     fc = 2 * 1 * L * N * 4 + 32 * 2 * L * N * 4 + 32 * 1 * L * N * 4
     assert st.mac_kernel_bytes(["split", "split"]) == conv + fc
+    # the matrix-core MAC reads and writes what the split one does (block sums, not outputs)
+    assert st.mac_kernel_bytes(["mfma", "split"]) == conv + fc
+    assert st.mac_kernel_bytes(["mfma", "split"], only=[True, False]) == conv
     assert st.modmuls() == 64 * 8 * 16 * L * N + 32 * 2 * 1 * L * N
     assert st.butterflies_fwd() == (64 * 4 * L * 2 + 32 * L * 2) * (N // 2) * 13
     assert st.tail_butterflies() == 64 * 16 * L * (M // 2) * 11 + 32 * 1 * L * (N // 2) * 13
@@ -107,3 +110,4 @@ def test_counter_traffic_follows_the_per_layer_forms(monkeypatch):
     assert bench.pmc_traffic("ntt_fwd") is None
     monkeypatch.setitem(bench.PMC_TRAFFIC, "ntt_fwd", _current("ntt_fwd"))
     assert bench.pmc_traffic("ntt_fwd") == bench.PMC_TRAFFIC["ntt_fwd"]["bytes_per_launch"]
+
