@@ -280,8 +280,8 @@ bool mac_lds_ok(const he_layer *ly, uint32_t B) {
     return B >= 2 && in.kind == HE_LAYER_CONV && in.flags == HE_PACK_CLASS_INTT && in.s >= 2 && in.N >= 256;
 }
 
-// the matrix-core batched MAC: residue-class conv layers with s >= 4, every input row's K = s
-// slots per block (the sum over rows of one block at most 32768 products)
+// the matrix-core batched MAC: residue-class conv layers with c_o a multiple of 8, s >= 4,
+// N / s >= 16 and at most 32768 products in a block sum (2 K_in s, the input share included)
 bool mac_mfma_layer_ok(const he_layer *ly, uint32_t B) {
     const he_layer_info &in = ly->info;
     return mac_lds_ok(ly, B) && mac_mfma_ok(B, ly->n_rows, 2 * in.K_in, in.N, in.s);
