@@ -180,7 +180,8 @@ def test_stress_x4_clients_decrypt_exact():
                 side[-1]["oc0"].append(oc0)
         print(f"encrypted layer {k}", flush=True)
 
-    res = serve.run_clients(v, bufs, C, streams=4, max_batch=16, budget=24 << 30, timeout_s=600)
+    # the bench's stress configuration: batches of up to 64 requests, which take the matrix-core MAC
+    res = serve.run_clients(v, bufs, C, streams=4, max_batch=64, budget=24 << 30, timeout_s=600)
     assert res["rc"] == 0 and (res["status"] == 0).all()
     st = serve.client_stats(res)
     print("stress stats:", st, flush=True)
